@@ -1,0 +1,116 @@
+"""Pins of the oracle's Algorithm 3 simulator: it must reach exactly the
+levels and (select, max) parents of the serial queue BFS (Lemmas 1 and 2), and
+its sieved messages must obey the sieve's invariants (CPU only)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_5542_amd import inputs
+
+
+def _graph(seed, scale, ef=8):
+    src, dst = inputs.rmat_tuples(scale, ef, seed=1000 + seed)
+    return 1 << scale, src, dst
+
+
+CASES = [(0, 6, 1), (1, 7, 2), (2, 8, 4), (3, 9, 8), (4, 9, 2), (5, 10, 4), (6, 10, 1), (7, 8, 2)]
+
+
+@pytest.mark.parametrize("seed,scale,p", CASES)
+def test_alg3_matches_queue_bfs(seed, scale, p):
+    n, src, dst = _graph(seed, scale)
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst)
+    roots = inputs.pick_roots(n, src, dst, 3, seed)
+    for root in roots:
+        root = int(root)
+        lev = adj.bfs(root)
+        par = adj.parents_max(lev, root)
+        r = adj.alg3(p, V, root, dump=True)
+        assert (r.level == lev).all()
+        assert (r.parent == par).all()
+        assert r.n_levels == lev.max() + 1
+        R = n // p
+        deg_blocks = V.sum(axis=0).reshape(n)  # blocks holding a neighbour of u
+        for k in range(1, r.n_levels):
+            for i in range(p):
+                piece = (lev[i * R:(i + 1) * R] == k).astype(np.uint8)
+                dest_count = np.zeros(R, dtype=np.int64)
+                for j in range(p):
+                    nw = r.words[k, i, j]
+                    w = r.streams[k, i, j, :nw]
+                    assert 1 <= nw <= R // 63 + 1
+                    got = oracle.wah_decode(w, R)
+                    # subset of the unsieved piece, and exactly piece . V_{j,i}
+                    assert not (got & ~piece).any()
+                    assert (got == (piece & V[j, i])).all()
+                    assert r.sieved_bits[k, i, j] == got.sum()
+                    if j != i:
+                        dest_count += got
+                # a frontier vertex goes to at most min(deg, p - 1) other processors
+                u = np.nonzero(piece)[0]
+                deg = np.array([adj.degree(i * R + x) for x in u], dtype=np.int64)
+                assert (dest_count[u] <= np.minimum(deg, p - 1)).all()
+                assert (dest_count[u] <= deg_blocks[i * R + u]).all()
+                uw = oracle.wah_encode(piece)
+                assert r.unsieved_words[k, i] == len(uw)
+        assert r.words[0].sum() == 0
+
+
+@pytest.mark.parametrize("seed,scale,p", [(11, 8, 4), (12, 9, 8)])
+def test_sieved_out_bits_have_no_edge_into_receiver(seed, scale, p):
+    n, src, dst = _graph(seed, scale)
+    R = n // p
+    V = oracle.directory(n, p, src, dst)
+    # brute force over the tuple list
+    has = np.zeros((p, n), dtype=bool)  # has[i, u]: u has a neighbour in R_i
+    has[dst // R, src] = True
+    has[src // R, dst] = True
+    for i in range(p):
+        for j in range(p):
+            assert (V[j, i].astype(bool) == has[j, i * R:(i + 1) * R]).all()
+
+
+def test_sieve_on_equals_sieve_off():
+    """Lemma 2: an all-ones directory (no sieve) gives the same levels/parents."""
+    n, src, dst = _graph(21, 9)
+    p = 4
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst)
+    ones = np.ones_like(V)
+    for root in inputs.pick_roots(n, src, dst, 4, 5):
+        a = adj.alg3(p, V, int(root))
+        b = adj.alg3(p, ones, int(root))
+        assert (a.level == b.level).all() and (a.parent == b.parent).all()
+        assert (a.sieved_bits <= b.sieved_bits).all()
+        assert a.words[:, ~np.eye(p, dtype=bool)].sum() <= b.words[:, ~np.eye(p, dtype=bool)].sum()
+
+
+def test_isolated_root_has_one_level():
+    n = 128
+    src = np.array([1, 2, 5, 5], dtype=np.int64)
+    dst = np.array([2, 3, 5, 9], dtype=np.int64)
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, 2, src, dst)
+    r = adj.alg3(2, V, 0)
+    assert r.n_levels == 1
+    assert r.level[0] == 0 and (r.level[1:] == -1).all()
+    assert r.words.sum() == 0
+
+
+def test_level_bytes_accounting():
+    n, src, dst = _graph(31, 10)
+    p = 4
+    R = n // p
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst)
+    r = adj.alg3(p, V, int(inputs.pick_roots(n, src, dst, 1, 9)[0]))
+    lb = r.level_bytes()
+    assert lb[0]["raw"] == 0 and lb[0]["wah_sieved"] == 0
+    for k in range(1, r.n_levels):
+        b = lb[k]
+        assert b["raw"] == p * (p - 1) * 8 * (R // 64)
+        assert b["wah_sieved"] == 8 * sum(r.words[k, i, j] for i in range(p) for j in range(p) if i != j)
+        assert b["self"] == 8 * sum(r.words[k, i, i] for i in range(p))
+        assert b["wah_sieved"] <= b["wah_unsieved"]
+        assert b["frontier"] == int((r.level == k).sum())

@@ -1,0 +1,161 @@
+"""Pins of the oracle against the paper's own worked examples (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _fig2_graph(g):
+    rows = g["adjacency_rows"]
+    n = g["n"]
+    A = np.array([[int(c) for c in r] for r in rows], dtype=np.uint8)
+    assert (A == A.T).all(), "Fig. 2 graph is undirected"
+    src, dst = np.nonzero(np.triu(A))
+    return n, A, src.astype(np.int64), dst.astype(np.int64)
+
+
+def test_fig2_frontiers(golden):
+    g = golden("fig2_example.json")
+    n, A, src, dst = _fig2_graph(g)
+    adj = oracle.Adjacency(n, src, dst)
+    level = adj.bfs(g["root"])
+    for k, members in g["frontiers"].items():
+        assert sorted(np.nonzero(level == int(k))[0].tolist()) == members
+    assert (level >= 0).all()
+
+
+def test_fig2_first_spmv(golden):
+    """The printed product A^T (x) f_L0 . not(pi_0) = f_L1, via Alg. 3 with p = 1."""
+    g = golden("fig2_example.json")
+    n, A, src, dst = _fig2_graph(g)
+    s = g["first_spmv"]
+    assert [1 - x for x in s["not_pi_0"]] == s["f_L0"]
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, 1, src, dst)
+    r = adj.alg3(1, V, g["root"])
+    assert (r.level == 1).astype(int).tolist() == s["f_L1"]
+
+
+def test_fig2_parents_max(golden):
+    g = golden("fig2_example.json")
+    n, A, src, dst = _fig2_graph(g)
+    adj = oracle.Adjacency(n, src, dst)
+    level = adj.bfs(g["root"])
+    parent = adj.parents_max(level, g["root"])
+    assert parent.tolist() == g["parent_max_derived"]
+    # vertex 1 has two candidate parents (6 and 7) on level 2: the max rule picks 7
+    assert parent[1] == 7
+    assert oracle.validate(n, src, dst, g["root"], level, parent) == 0
+
+
+def test_fig2_subblock_and_directory(golden):
+    g = golden("fig2_example.json")
+    n, A, src, dst = _fig2_graph(g)
+    part = g["partition"]
+    p = len(part)
+    # A_{4,2}: rows of P_4, columns of P_2 (1-based names, 0-based lists)
+    A42 = A[np.ix_(part[3], part[1])]
+    assert A42.tolist() == g["A_4_2"]
+    V = oracle.directory(n, p, src, dst)
+    assert V[3, 1].tolist() == g["V_4_2"]
+    # column k of A_{4,2} has a non-zero iff V_{4,2}[k] = 1 (Eq. dir-vec)
+    assert (A42.any(axis=0).astype(int)).tolist() == g["V_4_2"]
+    for i, row in g["directory_derived"].items():
+        if i.startswith("_"):
+            continue
+        for j, vec in row.items():
+            assert V[int(i) - 1, int(j) - 1].tolist() == vec, (i, j)
+
+
+def test_fig2_sieve(golden):
+    """f_2 = (1,1) is sieved to f_{2,4} = (0,1): P_4 only needs v_3 from P_2."""
+    g = golden("fig2_example.json")
+    n, A, src, dst = _fig2_graph(g)
+    p = 4
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst)
+    r = adj.alg3(p, V, g["root"], dump=True)
+    assert r.n_levels == 4
+    R = n // p
+    # P_2's level-1 piece
+    assert (r.level[R:2 * R] == 1).astype(int).tolist() == g["f_2_level1"]
+    words = r.streams[1, 1, 3, : r.words[1, 1, 3]]
+    got = oracle.wah_decode(words, R)
+    assert got.tolist() == g["f_2_4_sieved"]
+    assert [1 * R + k for k in range(R) if got[k]] == g["P4_needs_from_P2"]
+    # every derived message of the example
+    for k, senders in g["messages_derived"].items():
+        if k.startswith("_"):
+            continue
+        for i, dsts in senders.items():
+            for j, vec in dsts.items():
+                kk, ii, jj = int(k), int(i) - 1, int(j) - 1
+                w = r.streams[kk, ii, jj, : r.words[kk, ii, jj]]
+                assert oracle.wah_decode(w, R).tolist() == vec, (k, i, j)
+                assert r.sieved_bits[kk, ii, jj] == sum(vec)
+    # no message carries level 0 (the source is set everywhere without one)
+    assert r.words[0].sum() == 0
+
+
+def _matches(value, nbytes, unit):
+    scale = {"B": 0, "KB": 1, "MB": 2, "GB": 3}[unit]
+    digits = len(str(value).split(".")[1]) if "." in str(value) else 0
+    for base in (1024, 1000):
+        x = nbytes / base ** scale
+        if round(x, digits) == value or math.floor(x * 10 ** digits) / 10 ** digits == value:
+            return True
+    return False
+
+
+def test_table2_byte_arithmetic(golden):
+    t = golden("table2_sizes.json")
+    N = t["n_vertices"]
+    assert sum(r["count"] for r in t["levels"]) == t["total_count"] == N
+    bm = oracle.bitmap_bytes(N)
+    assert bm == 206454130
+    for row in t["levels"]:
+        assert _matches(*row["bitmap"][:1], bm, row["bitmap"][1])
+        if row["sparse"] is not None:
+            v, unit = row["sparse"]
+            assert _matches(v, oracle.sparse_vector_bytes(row["count"]), unit), row
+    assert _matches(t["total_bitmap"][0], len(t["levels"]) * bm, t["total_bitmap"][1])
+    # the readings of the garbled cells
+    assert abs(oracle.sparse_vector_bytes(235274348) / 2 ** 30 - 1.75) < 0.01
+    assert abs(oracle.sparse_vector_bytes(N) / 2 ** 30 - 12.3) < 0.01
+    s = t["bitmap_at_scale"]
+    assert oracle.bitmap_bytes(2 ** 26) == s["26"][0] * 2 ** 20
+    assert oracle.bitmap_bytes(2 ** 33) == s["33"][0] * 2 ** 30
+
+
+def test_table3_wah_toy(golden):
+    t = golden("wah_examples.json")["toy"]
+    bits = np.array([int(c) for c in t["bits"]], dtype=np.uint8)
+    words = oracle.wah_encode(bits, t["word_bits"], t["fill_bit_field"])
+    assert [format(int(w), "04b") for w in words] == t["words"]
+    back = oracle.wah_decode(words, len(bits), t["word_bits"], t["fill_bit_field"])
+    assert back.tolist() == bits.tolist()
+    # the groups of the second row of Table 3
+    g = t["word_bits"] - 1
+    grp = [t["bits"][i:i + g] for i in range(0, len(t["bits"]), g)]
+    assert grp == t["groups"]
+
+
+def test_wah32_example(golden):
+    t = golden("wah_examples.json")["w32"]
+    bits = np.concatenate([np.full(c, b, dtype=np.uint8) for b, c in t["runs"]])
+    assert len(bits) == 128
+    words = oracle.wah_encode(bits, t["word_bits"], t["fill_bit_field"])
+    assert [format(int(w), "08X") for w in words] == t["words_hex"]
+    back = oracle.wah_decode(words, len(bits), t["word_bits"], t["fill_bit_field"])
+    assert (back == bits).all()
+    # the row of literal words: every 31-bit group written as a literal
+    g = t["word_bits"] - 1
+    lits = []
+    for x in range(len(bits) // g):
+        w = 0
+        for tt in range(g):
+            w |= int(bits[x * g + tt]) << (g - 1 - tt)
+        lits.append(format(w, "08X"))
+    assert lits == t["literal_hex"][:len(lits)]
