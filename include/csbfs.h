@@ -1,0 +1,261 @@
+/*
+ * csbfs -- compression + sieve breadth-first search on one MI355X (gfx950).
+ *
+ * C ABI of the library built from paper_1208_5542_amd/csrc/csbfs. It follows
+ * Lv, Tan, Chen and Sun, "Compression and Sieve: Reducing Communication in
+ * Parallel Breadth First Search on Distributed Memory Systems" (2012):
+ * Algorithm 3 (Sec. V.B) over p virtual processors held as buffers on one
+ * GPU. Processor P_i owns the contiguous vertex range
+ * R_i = [i*n/p, (i+1)*n/p). Every level runs top-down expansion over the
+ * sub-blocks A_{i,j} (Eq. sub-block), the mask and update of the visited
+ * vector, the frontier-size reduction, the sieve of every outgoing message
+ * with the cross directory (Eq. dir-vec, Eq. cross-dir), WAH compression
+ * (Sec. IV, Table 3), and decompression into the receivers' frontier views.
+ * Messages are never sent anywhere: their bytes are counted.
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int status: CSBFS_OK (0) or a negative
+ *     CSBFS_E* code. csbfs_last_error() gives a thread-local message for the
+ *     most recent failure on the calling thread. No C++ exception crosses the
+ *     ABI. On failure the contents of output buffers are unspecified, and
+ *     nothing the caller owns is freed.
+ *   - Pointers documented as "device" are HIP device (or managed) memory of
+ *     the current device; "host" pointers are ordinary CPU memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued on it only; calls documented as blocking
+ *     synchronize that stream (and nothing else) before returning.
+ *   - Bit vectors are arrays of uint64 words: bit k of a vector is bit k % 64
+ *     of word k / 64.
+ *   - Vertex ids are int64 at the interface and must be < 2^31.
+ *   - The library allocates device memory only in csbfs_graph_build and
+ *     csbfs_engine_create; csbfs_bfs and the codec calls allocate nothing.
+ *
+ * The WAH-64 stream format (Sec. IV, Table 3 and the 32-bit example in the
+ * source of that table). A stream encodes N bits b[0..N) as 63-bit groups;
+ * G = floor(N/63) full groups, r = N - 63*G bits left over.
+ *   literal word: bit 63 = 0; bit (62 - t) = b[63x + t], t = 0..62, for one
+ *                 group x that is neither all 0 nor all 1;
+ *   fill word:    bit 63 = 1; bit 62 = the fill bit; bits 61..0 = c >= 1, a
+ *                 maximal run of c groups that are all equal to the fill bit
+ *                 (a run of one group is a fill too);
+ *   active word:  present iff r > 0, always the last word; bit (r - 1 - t) =
+ *                 b[63G + t] for t < r, all other bits 0.
+ * A stream of N bits never has more than floor(N/63) + 1 words.
+ */
+#ifndef CSBFS_H
+#define CSBFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSBFS_VERSION 10000 /* 1.0.0 */
+
+#define CSBFS_OK 0
+#define CSBFS_EINVAL (-1)    /* null pointer, bad size or bad flag */
+#define CSBFS_ERANGE (-2)    /* root or tuple id outside [0, n); n, p not admissible */
+#define CSBFS_ENOSPACE (-3)  /* caller buffer or workspace too small */
+#define CSBFS_EHIP (-4)      /* HIP runtime error; see csbfs_last_error() */
+#define CSBFS_EOVERFLOW (-5) /* a sub-block has 2^31 or more adjacency entries */
+#define CSBFS_ECORRUPT (-6)  /* a WAH stream failed validation while decoding */
+
+/* Library version as CSBFS_VERSION. */
+int csbfs_version(void);
+
+/* Static text for a status code (never NULL). */
+const char *csbfs_strerror(int status);
+
+/* Thread-local message describing the last failure on this thread ("" if none). */
+const char *csbfs_last_error(void);
+
+/* ======================================================================== */
+/* Graph: the p x p sub-block grid of an undirected graph.                  */
+/* ======================================================================== */
+
+typedef struct csbfs_graph csbfs_graph;
+
+/*
+ * Partition and store an undirected graph (Sec. V.A, Eq. abc and Eq.
+ * sub-block; the tuple list to CSR step of Sec. VII.A).
+ *
+ *   src, dst  device int64[n_tuples]: tuple t is the undirected edge
+ *             {src[t], dst[t]}; duplicates and self-loops are kept (a
+ *             self-loop is stored twice in its row).
+ *   n         vertex count; 64 <= n < 2^31.
+ *   p         virtual processor count; n % p == 0 and (n / p) % 64 == 0.
+ *   out       host: receives the graph handle.
+ *
+ * Block (i, j) holds, for every source u in R_j, its neighbours in R_i as a
+ * CSR row (int32 row offsets, uint32 local column ids). The directory vector
+ * V_{i,j} (Eq. dir-vec) is the non-empty-row bitmap of block (i, j). The
+ * input buffers are only read and may be freed after the call. Blocking.
+ * Errors: EINVAL (null pointers, n_tuples < 0), ERANGE (n or p not
+ * admissible, a tuple id outside [0, n)), EOVERFLOW, EHIP.
+ */
+int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t n_tuples, int64_t n,
+                      int32_t p, void *stream, csbfs_graph **out);
+
+/* Release a graph and all its device memory. NULL is accepted. Blocking. */
+int csbfs_graph_free(csbfs_graph *g);
+
+typedef struct csbfs_graph_info {
+    int64_t n;              /* vertices */
+    int32_t p;              /* virtual processors; p * p sub-blocks */
+    int32_t reserved;
+    int64_t range;          /* |R_i| = n / p */
+    int64_t n_tuples;       /* input tuples */
+    int64_t nnz;            /* adjacency entries over all blocks = 2 * n_tuples */
+    int64_t max_block_nnz;  /* largest sub-block */
+    int64_t device_bytes;   /* device memory held by the graph */
+} csbfs_graph_info;
+
+/* Sizes of a built graph (host call, no device work). */
+int csbfs_graph_get_info(const csbfs_graph *g, csbfs_graph_info *info);
+
+/*
+ * Copy the directory out: dst device uint64[p * p * (n / p) / 64]; the words
+ * of V_{i,j} start at (i * p + j) * (n / p) / 64 (Eq. dir-vec). cap_words is
+ * the capacity of dst. Errors: EINVAL, ENOSPACE, EHIP. Asynchronous.
+ */
+int csbfs_graph_copy_directory(const csbfs_graph *g, uint64_t *dst, int64_t cap_words,
+                               void *stream);
+
+/*
+ * Copy sub-block (i, j) out: row_ptr device int32[n/p + 1] (row_ptr[0] = 0),
+ * col device uint32[cap] (local ids in R_i; order within a row unspecified),
+ * nnz_out host int64. Blocking. Errors: EINVAL, ERANGE (i or j outside
+ * [0, p)), ENOSPACE (cap < block size; nnz_out still set), EHIP.
+ */
+int csbfs_graph_copy_block(const csbfs_graph *g, int32_t i, int32_t j, int32_t *row_ptr,
+                           uint32_t *col, int64_t cap, int64_t *nnz_out, void *stream);
+
+/*
+ * TEPS numerator (Sec. VII.A): the number of input tuples inside the
+ * component reached by a search whose level vector is `level` (device
+ * int32[n], -1 = unreached), duplicates and self-loops included. Blocking.
+ * Errors: EINVAL, EHIP.
+ */
+int csbfs_count_traversed_tuples(const csbfs_graph *g, const int32_t *level, int64_t *m_out,
+                                 void *stream);
+
+/* ======================================================================== */
+/* Engine: per-graph workspace for repeated single-source searches.          */
+/* ======================================================================== */
+
+typedef struct csbfs_engine csbfs_engine;
+
+/* Engine flags. */
+#define CSBFS_FLAG_TIMING 1u       /* record per-kernel times into the level stats */
+#define CSBFS_FLAG_KEEP_STREAMS 2u /* keep every level's WAH streams for copy-out */
+#define CSBFS_FLAG_NO_SIEVE 4u     /* all-ones directory: Alg. 2 messages (no sieve) */
+
+/*
+ * Allocate the workspace of Algorithm 3 for graph g: visited vector pi,
+ * frontier pieces f_i, the temporary t_i, the p frontier views (p * n bits),
+ * the WAH stream arena (p * p streams of floor((n/p)/63) + 1 words, times
+ * max_levels with CSBFS_FLAG_KEEP_STREAMS), the expansion work queue and the
+ * per-level counters for up to max_levels levels (1 <= max_levels <= 65536).
+ * The graph must outlive the engine. Blocking. Errors: EINVAL, EHIP.
+ */
+int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags,
+                        csbfs_engine **out);
+
+/* Release an engine. NULL is accepted. Blocking. */
+int csbfs_engine_free(csbfs_engine *e);
+
+/* Counters of one BFS level k: the frontier f^k and the messages carrying it. */
+typedef struct csbfs_level_stats {
+    int64_t frontier;           /* |f^k|; 1 at level 0 */
+    int64_t edges;              /* adjacency entries scanned when expanding f^k */
+    int64_t sieved_bits;        /* sum over i != j of ones(f_i^k . V_{j,i}) */
+    int64_t unsieved_bits;      /* (p - 1) * |f^k|: ones the Allgatherv of Alg. 1 carries */
+    int64_t raw_bytes;          /* p (p - 1) 8 ceil(|R|/64): Alg. 1 bitmap bytes */
+    int64_t wah_unsieved_bytes; /* sum over i != j of 8 |WAH(f_i^k)|: Alg. 2 bytes */
+    int64_t wah_sieved_bytes;   /* sum over i != j of 8 |WAH(f_i^k . V_{j,i})|: Alg. 3 bytes */
+    int64_t self_bytes;         /* sum over i of 8 |WAH(f_i^k . V_{i,i})| (never sent) */
+    int64_t max_rank_bytes;     /* max over i of Alg. 3 bytes sent plus received by P_i */
+    float ms_expand;            /* expansion of f^(k-1) that produced f^k (TIMING) */
+    float ms_update;            /* mask, visit update and reduction (TIMING) */
+    float ms_compress;          /* sieve + WAH encode of the f^k messages (TIMING) */
+    float ms_decode;            /* decode/merge of the f^k messages (TIMING) */
+} csbfs_level_stats;
+
+/*
+ * One breadth-first search from `root` (Algorithm 3; the problem statement of
+ * Sec. II and Algorithm 1: discover every vertex reachable from s).
+ *
+ *   level   device int32[n]: hop distance from root, -1 if unreachable.
+ *   parent  device int32[n]: parent[root] = root; for every other reached v,
+ *           the highest-labelled neighbour on level[v] - 1 (the (select, max)
+ *           semiring of Sec. III.A); -1 if unreachable.
+ *   stats   host csbfs_level_stats[stats_cap] or NULL: stats[k] for levels
+ *           k < min(n_levels, stats_cap, max_levels of the engine).
+ *   n_levels host: number of levels (max level + 1), whatever stats_cap is.
+ *
+ * Blocking: the level loop reads the frontier size back after each update
+ * (the "reducing" step of Sec. VII.B). Concurrent calls on one engine race;
+ * distinct engines may run concurrently on distinct streams. Errors: EINVAL,
+ * ERANGE (root outside [0, n)), ECORRUPT, EHIP.
+ */
+int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t *parent,
+              csbfs_level_stats *stats, int32_t stats_cap, int32_t *n_levels, void *stream);
+
+/*
+ * Word counts of the last search's streams: words host int32[cap_levels * p
+ * * p]; words[(k * p + i) * p + j] = words of the stream from P_i to P_j
+ * carrying level k (0 for k = 0, which is seeded and never sent). Levels
+ * beyond the engine's max_levels read 0. Blocking. Errors: EINVAL.
+ */
+int csbfs_engine_stream_words(const csbfs_engine *e, int32_t *words, int32_t cap_levels);
+
+/*
+ * Copy the stream from P_i to P_j that carried level k in the last search
+ * (needs CSBFS_FLAG_KEEP_STREAMS): dst device uint64[cap_words]; n_words_out
+ * host. Blocking. Errors: EINVAL (flag missing, k/i/j out of range),
+ * ENOSPACE, EHIP.
+ */
+int csbfs_engine_copy_stream(const csbfs_engine *e, int32_t k, int32_t i, int32_t j,
+                             uint64_t *dst, int64_t cap_words, int64_t *n_words_out,
+                             void *stream);
+
+/* ======================================================================== */
+/* WAH-64 codec on device buffers (Sec. IV).                                */
+/* ======================================================================== */
+
+/* Largest stream for nbits bits: floor(nbits/63) + 1 words. */
+int64_t csbfs_wah_capacity(int64_t nbits);
+
+/* Device scratch bytes the two codec calls need for nbits bits. */
+size_t csbfs_wah_workspace_bytes(int64_t nbits);
+
+/*
+ * Sieve and compress: encode (bits AND mask) over nbits bits (mask NULL means
+ * no sieve) as one WAH-64 stream (Alg. 3, sieve then Compress).
+ *   bits, mask  device uint64[ceil(nbits/64)]; bits at or past nbits are ignored.
+ *   out         device uint64[cap_words], cap_words >= csbfs_wah_capacity(nbits).
+ *   n_words     device int64[1]: receives the stream length in words.
+ *   workspace   device scratch of ws_bytes >= csbfs_wah_workspace_bytes(nbits).
+ * Asynchronous. Errors: EINVAL, ENOSPACE, EHIP.
+ */
+int csbfs_wah_encode(const uint64_t *bits, const uint64_t *mask, int64_t nbits, uint64_t *out,
+                     int64_t cap_words, int64_t *n_words, void *workspace, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * Uncompress: OR the nbits bits of a WAH-64 stream of n_words words into dst
+ * (device uint64[ceil(nbits/64)]; zero it first for a plain decode).
+ *   status  device int32[1]: set to 0 if the stream is a valid encoding of
+ *           exactly nbits bits, non-zero otherwise (dst then unspecified).
+ * Asynchronous. Errors: EINVAL, ENOSPACE, EHIP.
+ */
+int csbfs_wah_decode_or(const uint64_t *words, int64_t n_words, int64_t nbits, uint64_t *dst,
+                        int32_t *status, void *workspace, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSBFS_H */

@@ -1,0 +1,271 @@
+"""Thin ctypes binding of libcsbfs.so (include/csbfs.h).
+
+Argument marshalling only: every step of the search runs in the library's HIP
+kernels. torch provides device memory (tensors' data pointers) and the current
+stream. Importing this module does not touch the GPU; the library is loaded
+on first use and a missing library raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcsbfs.so")
+
+OK, EINVAL, ERANGE, ENOSPACE, EHIP, EOVERFLOW, ECORRUPT = 0, -1, -2, -3, -4, -5, -6
+FLAG_TIMING, FLAG_KEEP_STREAMS, FLAG_NO_SIEVE = 1, 2, 4
+
+_lib = None
+
+
+class CsbfsError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("range", ctypes.c_int64), ("n_tuples", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("max_block_nnz", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+class LevelStats(ctypes.Structure):
+    _fields_ = [("frontier", ctypes.c_int64), ("edges", ctypes.c_int64),
+                ("sieved_bits", ctypes.c_int64), ("unsieved_bits", ctypes.c_int64),
+                ("raw_bytes", ctypes.c_int64), ("wah_unsieved_bytes", ctypes.c_int64),
+                ("wah_sieved_bytes", ctypes.c_int64), ("self_bytes", ctypes.c_int64),
+                ("max_rank_bytes", ctypes.c_int64), ("ms_expand", ctypes.c_float),
+                ("ms_update", ctypes.c_float), ("ms_compress", ctypes.c_float),
+                ("ms_decode", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+def lib():
+    """Load libcsbfs.so (after torch, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first "
+                           "(there is no fallback path)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                             ctypes.c_size_t)
+    sig = {
+        "csbfs_version": ([], ctypes.c_int),
+        "csbfs_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "csbfs_last_error": ([], ctypes.c_char_p),
+        "csbfs_graph_build": ([vp, vp, i64, i64, i32, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "csbfs_graph_free": ([vp], ctypes.c_int),
+        "csbfs_graph_get_info": ([vp, ctypes.POINTER(GraphInfo)], ctypes.c_int),
+        "csbfs_graph_copy_directory": ([vp, vp, i64, vp], ctypes.c_int),
+        "csbfs_graph_copy_block": ([vp, i32, i32, vp, vp, i64, ctypes.POINTER(i64), vp], ctypes.c_int),
+        "csbfs_count_traversed_tuples": ([vp, vp, ctypes.POINTER(i64), vp], ctypes.c_int),
+        "csbfs_engine_create": ([vp, i32, u32, ctypes.POINTER(vp)], ctypes.c_int),
+        "csbfs_engine_free": ([vp], ctypes.c_int),
+        "csbfs_bfs": ([vp, i64, vp, vp, ctypes.POINTER(LevelStats), i32, ctypes.POINTER(i32), vp],
+                      ctypes.c_int),
+        "csbfs_engine_stream_words": ([vp, vp, i32], ctypes.c_int),
+        "csbfs_engine_copy_stream": ([vp, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp],
+                                     ctypes.c_int),
+        "csbfs_wah_capacity": ([i64], i64),
+        "csbfs_wah_workspace_bytes": ([i64], sz),
+        "csbfs_wah_encode": ([vp, vp, i64, vp, i64, vp, vp, sz, vp], ctypes.c_int),
+        "csbfs_wah_decode_or": ([vp, i64, i64, vp, vp, vp, sz, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        L = lib()
+        raise CsbfsError(rc, where, f"{L.csbfs_strerror(rc).decode()}: {L.csbfs_last_error().decode()}")
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "need a contiguous device tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def version() -> int:
+    return lib().csbfs_version()
+
+
+def strerror(status: int) -> str:
+    return lib().csbfs_strerror(status).decode()
+
+
+class Graph:
+    """The p x p sub-block grid of an undirected graph (csbfs_graph_build)."""
+
+    def __init__(self, src: torch.Tensor, dst: torch.Tensor, n: int, p: int, stream=None):
+        assert src.dtype == torch.int64 and dst.dtype == torch.int64 and src.shape == dst.shape
+        h = ctypes.c_void_p()
+        _check(lib().csbfs_graph_build(_ptr(src), _ptr(dst), src.numel(), n, p, _stream(stream),
+                                       ctypes.byref(h)), "csbfs_graph_build")
+        self._h = h
+        info = GraphInfo()
+        _check(lib().csbfs_graph_get_info(h, ctypes.byref(info)), "csbfs_graph_get_info")
+        self.info = info
+        self.n, self.p, self.range = int(info.n), int(info.p), int(info.range)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().csbfs_graph_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def directory(self, stream=None) -> torch.Tensor:
+        """V_{i,j} words, shape (p, p, n/p/64), uint64 bit patterns in int64."""
+        W = self.range // 64
+        out = torch.empty(self.p * self.p * W, dtype=torch.int64, device="cuda")
+        _check(lib().csbfs_graph_copy_directory(self._h, _ptr(out), out.numel(), _stream(stream)),
+               "csbfs_graph_copy_directory")
+        return out.view(self.p, self.p, W)
+
+    def block(self, i: int, j: int, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+        """CSR of sub-block (i, j): (row_ptr int32[R+1], col int32 local ids)."""
+        rp = torch.empty(self.range + 1, dtype=torch.int32, device="cuda")
+        nnz = ctypes.c_int64()
+        rc = lib().csbfs_graph_copy_block(self._h, i, j, _ptr(rp), None, 0, ctypes.byref(nnz),
+                                          _stream(stream))
+        if rc not in (OK, ENOSPACE):
+            _check(rc, "csbfs_graph_copy_block")
+        col = torch.empty(max(int(nnz.value), 1), dtype=torch.int32, device="cuda")
+        _check(lib().csbfs_graph_copy_block(self._h, i, j, _ptr(rp), _ptr(col), col.numel(),
+                                            ctypes.byref(nnz), _stream(stream)),
+               "csbfs_graph_copy_block")
+        return rp, col[: int(nnz.value)]
+
+    def traversed_tuples(self, level: torch.Tensor, stream=None) -> int:
+        m = ctypes.c_int64()
+        _check(lib().csbfs_count_traversed_tuples(self._h, _ptr(level), ctypes.byref(m),
+                                                  _stream(stream)), "csbfs_count_traversed_tuples")
+        return int(m.value)
+
+
+@dataclass
+class BfsResult:
+    level: torch.Tensor
+    parent: torch.Tensor
+    n_levels: int
+    stats: list[dict]
+
+
+class Engine:
+    """Workspace for repeated searches on one graph (csbfs_engine_create)."""
+
+    def __init__(self, graph: Graph, max_levels: int = 64, flags: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().csbfs_engine_create(graph.handle, max_levels, flags, ctypes.byref(h)),
+               "csbfs_engine_create")
+        self._h = h
+        self.graph = graph
+        self.max_levels = max_levels
+        self.flags = flags
+        self._stats = (LevelStats * max_levels)()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().csbfs_engine_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bfs(self, root: int, level: torch.Tensor | None = None, parent: torch.Tensor | None = None,
+            stream=None, with_stats: bool = True) -> BfsResult:
+        n = self.graph.n
+        if level is None:
+            level = torch.empty(n, dtype=torch.int32, device="cuda")
+        if parent is None:
+            parent = torch.empty(n, dtype=torch.int32, device="cuda")
+        nl = ctypes.c_int32()
+        cap = self.max_levels if with_stats else 0
+        _check(lib().csbfs_bfs(self._h, int(root), _ptr(level), _ptr(parent),
+                               self._stats if with_stats else None, cap, ctypes.byref(nl),
+                               _stream(stream)), "csbfs_bfs")
+        n_levels = int(nl.value)
+        stats = [self._stats[k].as_dict() for k in range(min(n_levels, cap))]
+        return BfsResult(level, parent, n_levels, stats)
+
+    def stream_words(self, n_levels: int):
+        import numpy as np
+        p = self.graph.p
+        out = np.zeros(n_levels * p * p, dtype=np.int32)
+        _check(lib().csbfs_engine_stream_words(self._h, out.ctypes.data_as(ctypes.c_void_p), n_levels),
+               "csbfs_engine_stream_words")
+        return out.reshape(n_levels, p, p)
+
+    def stream(self, k: int, i: int, j: int, stream=None) -> torch.Tensor:
+        cap = wah_capacity(self.graph.range)
+        out = torch.zeros(cap, dtype=torch.int64, device="cuda")
+        nw = ctypes.c_int64()
+        _check(lib().csbfs_engine_copy_stream(self._h, k, i, j, _ptr(out), cap, ctypes.byref(nw),
+                                              _stream(stream)), "csbfs_engine_copy_stream")
+        return out[: int(nw.value)]
+
+
+def wah_capacity(nbits: int) -> int:
+    return int(lib().csbfs_wah_capacity(nbits))
+
+
+def wah_workspace(nbits: int) -> torch.Tensor:
+    nb = int(lib().csbfs_wah_workspace_bytes(nbits))
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+
+
+def wah_encode(bits: torch.Tensor, nbits: int, mask: torch.Tensor | None = None,
+               workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """WAH-64 stream (int64 words holding uint64 patterns) of bits AND mask."""
+    cap = wah_capacity(nbits)
+    out = torch.empty(cap, dtype=torch.int64, device="cuda")
+    nw = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = workspace if workspace is not None else wah_workspace(nbits)
+    _check(lib().csbfs_wah_encode(_ptr(bits), _ptr(mask), nbits, _ptr(out), cap, _ptr(nw),
+                                  _ptr(ws), ws.numel(), _stream(stream)), "csbfs_wah_encode")
+    return out[: int(nw.item())]
+
+
+def wah_decode_or(words: torch.Tensor, nbits: int, dst: torch.Tensor | None = None,
+                  workspace: torch.Tensor | None = None, stream=None) -> tuple[torch.Tensor, int]:
+    """OR the decoded bits into dst (zeros if not given); returns (dst, status)."""
+    if dst is None:
+        dst = torch.zeros(max((nbits + 63) // 64, 1), dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = workspace if workspace is not None else wah_workspace(nbits)
+    _check(lib().csbfs_wah_decode_or(_ptr(words) if words.numel() else None, words.numel(), nbits,
+                                     _ptr(dst), _ptr(status), _ptr(ws), ws.numel(), _stream(stream)),
+           "csbfs_wah_decode_or")
+    return dst, int(status.item())

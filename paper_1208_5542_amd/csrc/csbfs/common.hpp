@@ -1,0 +1,89 @@
+// Internal declarations shared by the csbfs translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "csbfs.h"
+
+namespace csbfs {
+
+// ---------------------------------------------------------------- errors ---
+
+void set_error(const std::string &msg);
+int fail(int status, const std::string &msg);
+int hip_fail(hipError_t err, const char *what, const char *file, int line);
+
+#define CSBFS_HIP(call)                                                     \
+    do {                                                                    \
+        hipError_t _e = (call);                                             \
+        if (_e != hipSuccess)                                               \
+            return ::csbfs::hip_fail(_e, #call, __FILE__, __LINE__);        \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------------- constants ---
+
+constexpr int kWave = 64;             // gfx950 wavefront
+constexpr int kGroupBits = 63;        // WAH-64 group
+constexpr uint64_t kFillFlag = 1ull << 63;
+constexpr uint64_t kFillBit = 1ull << 62;
+constexpr uint64_t kCountMask = (1ull << 62) - 1;
+constexpr uint64_t kMask63 = (1ull << 63) - 1;
+
+// Encoder tiling: a workgroup of kEncThreads threads classifies one segment
+// of kEncSeg groups, kEncGpt consecutive groups per thread.
+constexpr int kEncThreads = 256;
+constexpr int kEncGpt = 4;
+constexpr int kEncSeg = kEncThreads * kEncGpt;
+// Decoder tiling: a workgroup reads one chunk of kDecChunk stream words.
+constexpr int kDecThreads = 256;
+constexpr int kDecWpt = 4;
+constexpr int kDecChunk = kDecThreads * kDecWpt;
+
+inline int64_t wah_cap(int64_t nbits) { return nbits / kGroupBits + 1; }
+inline int64_t enc_segments(int64_t nbits) {
+    int64_t G = nbits / kGroupBits;
+    return G == 0 ? 1 : (G + kEncSeg - 1) / kEncSeg;
+}
+inline int64_t dec_chunks(int64_t nbits) { return (wah_cap(nbits) + kDecChunk - 1) / kDecChunk; }
+
+// ---------------------------------------------------------- WAH batches ---
+//
+// A batch holds S = P * P streams; stream s = i * P + j carries the piece of
+// processor i (bits_base + i * words_per_piece) sieved with the directory
+// vector V_{j,i} (mask_base + (j * P + i) * words_per_piece, or no mask), is
+// written to out_base + s * cap, and is decoded into dst_base + (j * P + i) *
+// words_per_piece (the receiver j's view of the range of i).
+
+struct WahBatch {
+    const uint64_t *bits_base;
+    const uint64_t *mask_base;  // nullable
+    uint64_t *out_base;
+    int64_t *n_words;           // device [S]
+    int64_t nbits;              // bits per piece
+    int64_t words_per_piece;    // ceil(nbits / 64)
+    int64_t cap;                // words per stream slot
+    int32_t P;
+    // encoder scratch: per (stream, segment) flag counts and first flagged group
+    int32_t *seg_count;         // device [S * nseg]
+    int32_t *seg_first;         // device [S * nseg]
+    int64_t nseg;
+    // decoder scratch: per (stream, chunk) group totals
+    int64_t *chunk_groups;      // device [S * nchunk]
+    int64_t nchunk;
+    uint64_t *dst_base;         // decoder output
+    int32_t *status;            // device [1], non-zero on a corrupt stream
+    // optional statistics (device, nullable)
+    unsigned long long *stat_sieved_bits;    // [S]
+    unsigned long long *stat_unsieved_words; // [P]: words of WAH(piece_i), no mask
+};
+
+int launch_wah_encode(const WahBatch &b, hipStream_t stream);
+int launch_wah_decode(const WahBatch &b, hipStream_t stream);
+
+}  // namespace csbfs

@@ -1,0 +1,392 @@
+// Graph partitioning: the p x p sub-block grid of Sec. V.A (Eq. abc, Eq.
+// sub-block), one CSR per block, and the directory vectors of Eq. dir-vec.
+//
+// Block b = i * P + j holds, for every source u in R_j (row u - j*R), its
+// neighbours v in R_i as local ids v - i*R. Tuple {u, v} contributes u -> v
+// to block (owner(v), owner(u)) and v -> u to block (owner(u), owner(v)); a
+// self-loop contributes twice to one row. Rows are built by a counting pass,
+// a per-block scan (tile sums, scan of tile sums, local scans) and a scatter.
+#include <vector>
+
+#include "graph.hpp"
+
+namespace csbfs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTileItems = 4;
+constexpr int kTile = kThreads * kTileItems;
+
+__device__ __forceinline__ int wave_incl_scan_ll(long long &v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        long long t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return 0;
+}
+
+__device__ long long block_excl_scan_ll(long long v, long long *total) {
+    __shared__ long long ws[kThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    long long incl = v;
+    wave_incl_scan_ll(incl);
+    if (lane == 63) ws[wid] = incl;
+    __syncthreads();
+    long long before = 0, tot = 0;
+    for (int k = 0; k < kThreads / 64; ++k) {
+        if (k < wid) before += ws[k];
+        tot += ws[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+__global__ void k_count(const int64_t *src, const int64_t *dst, int64_t m, int64_t n, int64_t R,
+                        int32_t P, int32_t *cnt, int32_t *err) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = src[t], v = dst[t];
+        if (u < 0 || u >= n || v < 0 || v >= n) {
+            *err = 1;
+            continue;
+        }
+        const int64_t ou = u / R, ov = v / R;
+        atomicAdd(&cnt[(ov * P + ou) * R + (u - ou * R)], 1);  // u -> v
+        atomicAdd(&cnt[(ou * P + ov) * R + (v - ov * R)], 1);  // v -> u
+    }
+}
+
+// tile sums of every block's row counts: sums[b * ntile + t]
+__global__ __launch_bounds__(kThreads) void k_tile_sum(const int32_t *cnt, int64_t R, int64_t ntile,
+                                                       long long *sums) {
+    const int64_t t = blockIdx.x, b = blockIdx.y;
+    long long s = 0;
+    for (int64_t k = threadIdx.x; k < kTile; k += kThreads) {
+        const int64_t u = t * kTile + k;
+        if (u < R) s += cnt[b * R + u];
+    }
+    __shared__ long long red[kThreads / 64];
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long tot = 0;
+        for (int k = 0; k < kThreads / 64; ++k) tot += red[k];
+        sums[b * ntile + t] = tot;
+    }
+}
+
+// in-place exclusive scan of each block's tile sums; block totals to nnz[b]
+__global__ __launch_bounds__(kThreads) void k_tile_scan(long long *sums, int64_t ntile,
+                                                        long long *nnz) {
+    const int64_t b = blockIdx.x;
+    long long carry = 0;
+    for (int64_t base = 0; base < ntile; base += kThreads) {
+        const int64_t t = base + threadIdx.x;
+        const long long v = t < ntile ? sums[b * ntile + t] : 0;
+        long long tot;
+        const long long ex = block_excl_scan_ll(v, &tot);
+        if (t < ntile) sums[b * ntile + t] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) nnz[b] = carry;
+}
+
+// row_ptr[b * (R + 1) + u] = exclusive prefix of row counts within block b;
+// the counts become the scatter cursors (cursor[u] = row_ptr[u]).
+__global__ __launch_bounds__(kThreads) void k_tile_apply(int32_t *cnt, int64_t R, int64_t ntile,
+                                                         const long long *sums, int32_t *row_ptr) {
+    const int64_t t = blockIdx.x, b = blockIdx.y;
+    const int64_t u0 = t * kTile + threadIdx.x * kTileItems;
+    long long v[kTileItems];
+    long long mine = 0;
+    for (int k = 0; k < kTileItems; ++k) {
+        const int64_t u = u0 + k;
+        v[k] = u < R ? cnt[b * R + u] : 0;
+        mine += v[k];
+    }
+    long long tot;
+    long long x = sums[b * ntile + t] + block_excl_scan_ll(mine, &tot);
+    for (int k = 0; k < kTileItems; ++k) {
+        const int64_t u = u0 + k;
+        if (u < R) {
+            row_ptr[b * (R + 1) + u] = (int32_t)x;
+            cnt[b * R + u] = (int32_t)x;
+            x += v[k];
+            if (u == R - 1) row_ptr[b * (R + 1) + R] = (int32_t)x;
+        }
+    }
+}
+
+__global__ void k_scatter(const int64_t *src, const int64_t *dst, int64_t m, int64_t R, int32_t P,
+                          int32_t *cursor, const int64_t *col_base, uint32_t *col) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = src[t], v = dst[t];
+        const int64_t ou = u / R, ov = v / R;
+        const int64_t b1 = ov * P + ou, b2 = ou * P + ov;
+        const int32_t p1 = atomicAdd(&cursor[b1 * R + (u - ou * R)], 1);
+        col[col_base[b1] + p1] = (uint32_t)(v - ov * R);
+        const int32_t p2 = atomicAdd(&cursor[b2 * R + (v - ov * R)], 1);
+        col[col_base[b2] + p2] = (uint32_t)(u - ou * R);
+    }
+}
+
+// V_{i,j}: bit u of block b's vector = row u of block b is non-empty.
+__global__ void k_directory(const int32_t *row_ptr, int64_t R, int64_t W, int64_t nblocks,
+                            uint64_t *dir) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w = wave; w < nblocks * W; w += nwaves) {
+        const int64_t b = w / W, q = w - b * W;
+        const int32_t *rp = row_ptr + b * (R + 1) + q * 64 + lane;
+        const bool nz = rp[1] > rp[0];
+        const uint64_t m = __ballot(nz);
+        if (lane == 0) dir[w] = m;
+    }
+}
+
+// deg[u] = adjacency entries of u over all blocks of its column; big[0] +=
+// the expansion-queue items the rows of u would need if all were expanded.
+__global__ void k_degree(const int32_t *row_ptr, int64_t R, int32_t P, int64_t n, int32_t *deg,
+                         unsigned long long *big_items) {
+    unsigned long long items = 0;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = u / R, ul = u - j * R;
+        int32_t d = 0;
+        for (int32_t i = 0; i < P; ++i) {
+            const int32_t *rp = row_ptr + ((int64_t)i * P + j) * (R + 1) + ul;
+            const int32_t len = rp[1] - rp[0];
+            d += len;
+            if (len > kBigRow) items += (len + kBigChunk - 1) / kBigChunk;
+        }
+        deg[u] = d;
+    }
+    for (int d = 32; d > 0; d >>= 1) items += __shfl_xor(items, d, 64);
+    if ((threadIdx.x & 63) == 0 && items) atomicAdd(big_items, items);
+}
+
+__global__ void k_count_m(const int32_t *level, const int32_t *deg, int64_t n,
+                          unsigned long long *out) {
+    unsigned long long s = 0;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x)
+        if (level[u] >= 0) s += (unsigned long long)deg[u];
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(out, s);
+}
+
+unsigned grid_for(int64_t items, int64_t per_block, unsigned cap = 65536) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    void *release() {
+        void *q = p;
+        p = nullptr;
+        return q;
+    }
+};
+
+}  // namespace
+
+int graph_device_check(const csbfs_graph *g) {
+    int dev = -1;
+    CSBFS_HIP(hipGetDevice(&dev));
+    if (dev != g->device) return fail(CSBFS_EINVAL, "graph was built on another device");
+    return CSBFS_OK;
+}
+
+}  // namespace csbfs
+
+using namespace csbfs;
+
+extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t n_tuples,
+                                 int64_t n, int32_t p, void *stream, csbfs_graph **out) {
+    if (!out) return fail(CSBFS_EINVAL, "csbfs_graph_build: out is NULL");
+    *out = nullptr;
+    if (n_tuples < 0 || (n_tuples > 0 && (!src || !dst)))
+        return fail(CSBFS_EINVAL, "csbfs_graph_build: null tuple arrays or negative count");
+    if (n < 64 || n >= ((int64_t)1 << 31))
+        return fail(CSBFS_ERANGE, "csbfs_graph_build: need 64 <= n < 2^31");
+    if (p < 1 || p > 64 || n % p != 0 || (n / p) % 64 != 0)
+        return fail(CSBFS_ERANGE, "csbfs_graph_build: need 1 <= p <= 64, p | n and 64 | n/p");
+    if (n_tuples > ((int64_t)1 << 40))
+        return fail(CSBFS_ERANGE, "csbfs_graph_build: too many tuples");
+    hipStream_t st = as_stream(stream);
+    const int64_t R = n / p, W = R / 64, B = (int64_t)p * p;
+
+    std::unique_ptr<csbfs_graph> g(new csbfs_graph());
+    CSBFS_HIP(hipGetDevice(&g->device));
+    g->n = n;
+    g->P = p;
+    g->R = R;
+    g->W = W;
+    g->n_tuples = n_tuples;
+
+    DevBuf cnt, sums, nnzb, err, rp, cb, col, dir, deg, scratch;
+    const int64_t ntile = (R + kTile - 1) / kTile;
+    CSBFS_HIP(hipMalloc(&cnt.p, sizeof(int32_t) * B * R));
+    CSBFS_HIP(hipMalloc(&sums.p, sizeof(long long) * B * ntile));
+    CSBFS_HIP(hipMalloc(&nnzb.p, sizeof(long long) * B));
+    CSBFS_HIP(hipMalloc(&err.p, sizeof(int32_t)));
+    CSBFS_HIP(hipMalloc(&rp.p, sizeof(int32_t) * B * (R + 1)));
+    CSBFS_HIP(hipMalloc(&cb.p, sizeof(int64_t) * (B + 1)));
+    CSBFS_HIP(hipMalloc(&dir.p, sizeof(uint64_t) * B * W));
+    CSBFS_HIP(hipMalloc(&deg.p, sizeof(int32_t) * n));
+    CSBFS_HIP(hipMalloc(&scratch.p, 256));
+    CSBFS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * B * R, st));
+    CSBFS_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
+
+    if (n_tuples > 0) {
+        hipLaunchKernelGGL(k_count, dim3(grid_for(n_tuples, kThreads)), dim3(kThreads), 0, st, src,
+                           dst, n_tuples, n, R, p, (int32_t *)cnt.p, (int32_t *)err.p);
+        CSBFS_HIP(hipGetLastError());
+    }
+    int32_t herr = 0;
+    CSBFS_HIP(hipMemcpyAsync(&herr, err.p, sizeof(herr), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    if (herr) return fail(CSBFS_ERANGE, "csbfs_graph_build: a tuple id is outside [0, n)");
+
+    hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)ntile, (unsigned)B), dim3(kThreads), 0, st,
+                       (const int32_t *)cnt.p, R, ntile, (long long *)sums.p);
+    CSBFS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)B), dim3(kThreads), 0, st, (long long *)sums.p,
+                       ntile, (long long *)nnzb.p);
+    CSBFS_HIP(hipGetLastError());
+    std::vector<long long> nnz(B);
+    CSBFS_HIP(hipMemcpyAsync(nnz.data(), nnzb.p, sizeof(long long) * B, hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    std::vector<int64_t> base(B + 1, 0);
+    int64_t maxb = 0;
+    for (int64_t b = 0; b < B; ++b) {
+        if (nnz[b] >= ((long long)1 << 31) - 1)
+            return fail(CSBFS_EOVERFLOW, "csbfs_graph_build: a sub-block has >= 2^31 entries");
+        base[b + 1] = base[b] + nnz[b];
+        if (nnz[b] > maxb) maxb = nnz[b];
+    }
+    const int64_t total = base[B];
+    CSBFS_HIP(hipMemcpyAsync(cb.p, base.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_tile_apply, dim3((unsigned)ntile, (unsigned)B), dim3(kThreads), 0, st,
+                       (int32_t *)cnt.p, R, ntile, (const long long *)sums.p, (int32_t *)rp.p);
+    CSBFS_HIP(hipGetLastError());
+    CSBFS_HIP(hipMalloc(&col.p, sizeof(uint32_t) * (total > 0 ? total : 1)));
+    if (n_tuples > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_tuples, kThreads)), dim3(kThreads), 0, st,
+                           src, dst, n_tuples, R, p, (int32_t *)cnt.p, (const int64_t *)cb.p,
+                           (uint32_t *)col.p);
+        CSBFS_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_directory, dim3(grid_for(B * W * 64, kThreads)), dim3(kThreads), 0, st,
+                       (const int32_t *)rp.p, R, W, B, (uint64_t *)dir.p);
+    CSBFS_HIP(hipGetLastError());
+    CSBFS_HIP(hipMemsetAsync(scratch.p, 0, 256, st));
+    hipLaunchKernelGGL(k_degree, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st,
+                       (const int32_t *)rp.p, R, p, n, (int32_t *)deg.p,
+                       (unsigned long long *)scratch.p);
+    CSBFS_HIP(hipGetLastError());
+    unsigned long long big_items = 0;
+    CSBFS_HIP(hipMemcpyAsync(&big_items, scratch.p, sizeof(big_items), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+
+    g->row_ptr = (int32_t *)rp.release();
+    g->col_base = (int64_t *)cb.release();
+    g->col_base_host = base;
+    g->col = (uint32_t *)col.release();
+    g->dir = (uint64_t *)dir.release();
+    g->deg = (int32_t *)deg.release();
+    g->scratch = (unsigned long long *)scratch.release();
+    g->nnz = total;
+    g->max_block_nnz = maxb;
+    g->big_items = (int64_t)big_items;
+    g->device_bytes = (int64_t)(sizeof(int32_t) * B * (R + 1) + sizeof(int64_t) * (B + 1) +
+                                sizeof(uint32_t) * total + sizeof(uint64_t) * B * W +
+                                sizeof(int32_t) * n + 256);
+    *out = g.release();
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_graph_free(csbfs_graph *g) {
+    if (!g) return CSBFS_OK;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g->row_ptr);
+    (void)hipFree(g->col_base);
+    (void)hipFree(g->col);
+    (void)hipFree(g->dir);
+    (void)hipFree(g->deg);
+    (void)hipFree(g->scratch);
+    delete g;
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_graph_get_info(const csbfs_graph *g, csbfs_graph_info *info) {
+    if (!g || !info) return fail(CSBFS_EINVAL, "csbfs_graph_get_info: null argument");
+    info->n = g->n;
+    info->p = g->P;
+    info->reserved = 0;
+    info->range = g->R;
+    info->n_tuples = g->n_tuples;
+    info->nnz = g->nnz;
+    info->max_block_nnz = g->max_block_nnz;
+    info->device_bytes = g->device_bytes;
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_graph_copy_directory(const csbfs_graph *g, uint64_t *dst, int64_t cap_words,
+                                          void *stream) {
+    if (!g || !dst) return fail(CSBFS_EINVAL, "csbfs_graph_copy_directory: null argument");
+    const int64_t words = (int64_t)g->P * g->P * g->W;
+    if (cap_words < words) return fail(CSBFS_ENOSPACE, "csbfs_graph_copy_directory: dst too small");
+    CSBFS_HIP(hipMemcpyAsync(dst, g->dir, sizeof(uint64_t) * words, hipMemcpyDeviceToDevice,
+                             as_stream(stream)));
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_graph_copy_block(const csbfs_graph *g, int32_t i, int32_t j, int32_t *row_ptr,
+                                      uint32_t *col, int64_t cap, int64_t *nnz_out, void *stream) {
+    if (!g || !row_ptr || !nnz_out || cap < 0)
+        return fail(CSBFS_EINVAL, "csbfs_graph_copy_block: null argument");
+    if (i < 0 || i >= g->P || j < 0 || j >= g->P)
+        return fail(CSBFS_ERANGE, "csbfs_graph_copy_block: block index outside [0, p)");
+    const int64_t b = (int64_t)i * g->P + j;
+    const int64_t nnz = g->col_base_host[b + 1] - g->col_base_host[b];
+    *nnz_out = nnz;
+    if (cap < nnz) return fail(CSBFS_ENOSPACE, "csbfs_graph_copy_block: col capacity too small");
+    if (nnz > 0 && !col) return fail(CSBFS_EINVAL, "csbfs_graph_copy_block: col is NULL");
+    hipStream_t st = as_stream(stream);
+    CSBFS_HIP(hipMemcpyAsync(row_ptr, g->row_ptr + b * (g->R + 1), sizeof(int32_t) * (g->R + 1),
+                             hipMemcpyDeviceToDevice, st));
+    if (nnz > 0)
+        CSBFS_HIP(hipMemcpyAsync(col, g->col + g->col_base_host[b], sizeof(uint32_t) * nnz,
+                                 hipMemcpyDeviceToDevice, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_count_traversed_tuples(const csbfs_graph *g, const int32_t *level,
+                                            int64_t *m_out, void *stream) {
+    if (!g || !level || !m_out) return fail(CSBFS_EINVAL, "csbfs_count_traversed_tuples: null argument");
+    hipStream_t st = as_stream(stream);
+    CSBFS_HIP(hipMemsetAsync(g->scratch, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_count_m, dim3(grid_for(g->n, kThreads, 4096)), dim3(kThreads), 0, st,
+                       level, (const int32_t *)g->deg, g->n, g->scratch);
+    CSBFS_HIP(hipGetLastError());
+    unsigned long long s = 0;
+    CSBFS_HIP(hipMemcpyAsync(&s, g->scratch, sizeof(s), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    // every tuple contributes two adjacency entries (a self-loop two in one row)
+    *m_out = (int64_t)(s / 2);
+    return CSBFS_OK;
+}

@@ -1,0 +1,233 @@
+"""GPU search against the oracle on small graphs: partition and directory,
+levels bit-exact, (select, max) parents exact, per-level streams
+byte-identical to the oracle's Algorithm 3, byte accounting, edge cases."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1208_5542_amd import inputs
+from tests.gpu_util import from_words, log, require_gpu, u64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _graph(scale, ef=16, seed=None):
+    src, dst = inputs.rmat_tuples(scale, ef, seed=seed)
+    return 1 << scale, src, dst
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64)).cuda()
+
+
+@pytest.mark.parametrize("scale,p", [(10, 1), (10, 2), (10, 4), (12, 8), (11, 4)])
+def test_directory_and_blocks(scale, p):
+    from paper_1208_5542_amd import csbfs
+    n, src, dst = _graph(scale)
+    log(f"graph build scale={scale} p={p}")
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    R = n // p
+    assert g.info.nnz == 2 * len(src)
+    V = oracle.directory(n, p, src, dst)
+    dirw = g.directory()
+    for i in range(p):
+        for j in range(p):
+            assert (from_words(dirw[i, j], R) == V[i, j]).all(), (i, j)
+    # rows of every block as multisets: u in R_j -> its neighbours in R_i
+    for i in range(p):
+        for j in range(p):
+            rp, col = g.block(i, j)
+            rp, col = rp.cpu().numpy(), col.cpu().numpy()
+            a = np.r_[src, dst]
+            b = np.r_[dst, src]
+            sel = (a // R == j) & (b // R == i)
+            exp = {}
+            for u, v in zip(a[sel] - j * R, b[sel] - i * R):
+                exp.setdefault(int(u), []).append(int(v))
+            assert rp[0] == 0 and rp[-1] == len(col)
+            for u in range(R):
+                got = sorted(col[rp[u]:rp[u + 1]].tolist())
+                assert got == sorted(exp.get(u, [])), (i, j, u)
+
+
+def _check_search(eng, g, n, p, src, dst, root, adj, V, keep=True, max_levels=64):
+    r = eng.bfs(root)
+    torch.cuda.synchronize()
+    lev = r.level.cpu().numpy()
+    par = r.parent.cpu().numpy()
+    ref = adj.alg3(p, V, root, max_levels=max_levels, dump=keep)
+    assert (lev == ref.level).all(), "level"
+    assert (par == ref.parent).all(), "parent"
+    assert r.n_levels == ref.n_levels
+    assert oracle.validate(n, src, dst, root, lev, par, ref.level) == 0
+    words = eng.stream_words(r.n_levels)
+    assert (words == ref.words).all(), "stream lengths"
+    if keep:
+        for k in range(1, r.n_levels):
+            for i in range(p):
+                for j in range(p):
+                    got = u64(eng.stream(k, i, j))
+                    exp = ref.streams[k, i, j, : ref.words[k, i, j]]
+                    assert got.tolist() == exp.tolist(), (k, i, j)
+    # byte accounting
+    lb = ref.level_bytes()
+    for k in range(r.n_levels):
+        s = r.stats[k]
+        assert s["frontier"] == lb[k]["frontier"]
+        assert s["wah_sieved_bytes"] == lb[k]["wah_sieved"]
+        assert s["self_bytes"] == lb[k]["self"]
+        assert s["raw_bytes"] == lb[k]["raw"]
+        assert s["wah_unsieved_bytes"] == lb[k]["wah_unsieved"]
+        assert s["max_rank_bytes"] == lb[k]["max_rank_volume"]
+        if k > 0:
+            off = ~np.eye(p, dtype=bool)
+            assert s["sieved_bits"] == int(ref.sieved_bits[k][off].sum())
+            assert s["unsieved_bits"] == (p - 1) * lb[k]["frontier"]
+    # edges scanned when expanding level k: adjacency of every level-k vertex
+    # inside the blocks whose view received it
+    assert g.traversed_tuples(r.level) == oracle.teps_m(src, dst, lev)
+    return r
+
+
+@pytest.mark.parametrize("scale,p,nroots", [(10, 1, 16), (10, 2, 4), (10, 4, 4), (11, 8, 3),
+                                            (12, 4, 3), (13, 2, 2)])
+def test_search_matches_oracle(scale, p, nroots):
+    from paper_1208_5542_amd import csbfs
+    n, src, dst = _graph(scale)
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    eng = csbfs.Engine(g, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS)
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst).reshape(-1)
+    roots = inputs.pick_roots(n, src, dst, nroots, inputs.graph_seed(scale) + 2)
+    for root in roots:
+        log(f"search scale={scale} p={p} root={int(root)}")
+        _check_search(eng, g, n, p, src, dst, int(root), adj, V)
+
+
+def test_sparse_graph_many_levels():
+    """A long path plus random chords: many levels, tiny frontiers."""
+    from paper_1208_5542_amd import csbfs
+    n, p = 4096, 4
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(n)
+    src = perm[:-1].astype(np.int64)
+    dst = perm[1:].astype(np.int64)
+    extra = rng.integers(0, n, (2, 40))
+    src = np.r_[src, extra[0]].astype(np.int64)
+    dst = np.r_[dst, extra[1]].astype(np.int64)
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    eng = csbfs.Engine(g, max_levels=4096, flags=csbfs.FLAG_KEEP_STREAMS)
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst).reshape(-1)
+    log("search long path")
+    r = _check_search(eng, g, n, p, src, dst, int(perm[0]), adj, V, keep=False, max_levels=4096)
+    assert r.n_levels > 50
+
+
+def test_stats_truncated_beyond_max_levels():
+    from paper_1208_5542_amd import csbfs
+    n, p = 1024, 2
+    src = np.arange(0, n - 1, dtype=np.int64)
+    dst = np.arange(1, n, dtype=np.int64)
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    eng = csbfs.Engine(g, max_levels=8)
+    r = eng.bfs(0)
+    assert r.n_levels == n
+    assert len(r.stats) == 8
+    assert (r.level.cpu().numpy() == np.arange(n)).all()
+    assert (r.parent.cpu().numpy()[1:] == np.arange(n - 1)).all()
+
+
+def test_high_degree_rows_use_chunk_queue():
+    """A star with a hub of degree >> the per-wave row limit."""
+    from paper_1208_5542_amd import csbfs
+    n, p = 1 << 14, 4
+    rng = np.random.default_rng(9)
+    hub = 77
+    leaves = rng.permutation(np.arange(n))[:9000]
+    leaves = leaves[leaves != hub]
+    src = np.r_[np.full(len(leaves), hub), rng.integers(0, n, 3000)].astype(np.int64)
+    dst = np.r_[leaves, rng.integers(0, n, 3000)].astype(np.int64)
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    eng = csbfs.Engine(g, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS)
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst).reshape(-1)
+    for root in (hub, int(leaves[0])):
+        log(f"star root={root}")
+        _check_search(eng, g, n, p, src, dst, root, adj, V)
+
+
+def test_isolated_root_and_empty_graph():
+    from paper_1208_5542_amd import csbfs
+    n, p = 256, 2
+    src = np.array([1, 2, 5], dtype=np.int64)
+    dst = np.array([2, 3, 5], dtype=np.int64)
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    eng = csbfs.Engine(g)
+    for root in (0, 5):  # no tuple at all / only a self-loop
+        r = eng.bfs(root)
+        lev = r.level.cpu().numpy()
+        assert r.n_levels == 1 and lev[root] == 0 and (np.delete(lev, root) == -1).all()
+        assert r.parent.cpu().numpy()[root] == root
+        assert r.stats[0]["frontier"] == 1
+    e = csbfs.Graph(torch.zeros(1, dtype=torch.int64, device="cuda")[:0],
+                    torch.zeros(1, dtype=torch.int64, device="cuda")[:0], 128, 2)
+    r = csbfs.Engine(e).bfs(127)
+    assert r.n_levels == 1
+
+
+def test_no_sieve_flag_gives_same_search():
+    from paper_1208_5542_amd import csbfs
+    n, src, dst = _graph(11)
+    p = 4
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    a = csbfs.Engine(g)
+    b = csbfs.Engine(g, flags=csbfs.FLAG_NO_SIEVE)
+    adj = oracle.Adjacency(n, src, dst)
+    ones = np.ones(p * n, dtype=np.uint8)
+    root = int(inputs.pick_roots(n, src, dst, 1, 1)[0])
+    ra, rb = a.bfs(root), b.bfs(root)
+    assert torch.equal(ra.level, rb.level) and torch.equal(ra.parent, rb.parent)
+    ref = adj.alg3(p, ones, root)
+    assert (b.stream_words(rb.n_levels) == ref.words).all()
+    for k in range(1, ra.n_levels):
+        assert ra.stats[k]["wah_sieved_bytes"] <= rb.stats[k]["wah_sieved_bytes"]
+        assert rb.stats[k]["wah_sieved_bytes"] == rb.stats[k]["wah_unsieved_bytes"]
+
+
+def test_deterministic_repeat():
+    from paper_1208_5542_amd import csbfs
+    n, src, dst = _graph(12)
+    g = csbfs.Graph(_dev(src), _dev(dst), n, 4)
+    eng = csbfs.Engine(g, flags=csbfs.FLAG_KEEP_STREAMS)
+    root = int(inputs.pick_roots(n, src, dst, 1, 3)[0])
+    r1 = eng.bfs(root)
+    l1, p1, w1 = r1.level.clone(), r1.parent.clone(), eng.stream_words(r1.n_levels)
+    s1 = [u64(eng.stream(k, 1, 2)).tolist() for k in range(1, r1.n_levels)]
+    r2 = eng.bfs(root)
+    assert torch.equal(l1, r2.level) and torch.equal(p1, r2.parent)
+    assert (w1 == eng.stream_words(r2.n_levels)).all()
+    assert s1 == [u64(eng.stream(k, 1, 2)).tolist() for k in range(1, r2.n_levels)]
+
+
+def test_error_statuses():
+    from paper_1208_5542_amd import csbfs
+    n, src, dst = _graph(10)
+    with pytest.raises(csbfs.CsbfsError) as ei:
+        csbfs.Graph(_dev(np.r_[src, [n]]), _dev(np.r_[dst, [0]]), n, 2)
+    assert ei.value.status == csbfs.ERANGE
+    g = csbfs.Graph(_dev(src), _dev(dst), n, 2)
+    eng = csbfs.Engine(g)
+    for bad in (-1, n):
+        with pytest.raises(csbfs.CsbfsError) as ei:
+            eng.bfs(bad)
+        assert ei.value.status == csbfs.ERANGE
+    with pytest.raises(csbfs.CsbfsError) as ei:
+        eng.stream(1, 0, 0)
+    assert ei.value.status == csbfs.EINVAL
