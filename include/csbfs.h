@@ -151,6 +151,13 @@ typedef struct csbfs_engine csbfs_engine;
 #define CSBFS_FLAG_TIMING 1u       /* record per-kernel times into the level stats */
 #define CSBFS_FLAG_KEEP_STREAMS 2u /* keep every level's WAH streams for copy-out */
 #define CSBFS_FLAG_NO_SIEVE 4u     /* all-ones directory: Alg. 2 messages (no sieve) */
+/* The (select, max) product of a level is evaluated either by pushing every
+ * source into parent[] with atomicMax ("sparse", the default) or by marking
+ * targets seen and letting each new vertex pull its highest frontier
+ * neighbour from its sorted rows ("dense"); both give identical results.
+ * These flags force one evaluation for every level. */
+#define CSBFS_FLAG_SPARSE_ONLY 8u
+#define CSBFS_FLAG_DENSE_ONLY 16u
 
 /*
  * Allocate the workspace of Algorithm 3 for graph g: visited vector pi,
@@ -166,10 +173,13 @@ int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags
 /* Release an engine. NULL is accepted. Blocking. */
 int csbfs_engine_free(csbfs_engine *e);
 
-/* Counters of one BFS level k: the frontier f^k and the messages carrying it. */
+/* Counters of one BFS level k: the frontier f^k, its expansion, and the
+ * messages carrying it (which exist for k >= 1; level 0 is seeded). */
 typedef struct csbfs_level_stats {
     int64_t frontier;           /* |f^k|; 1 at level 0 */
     int64_t edges;              /* adjacency entries scanned when expanding f^k */
+    int64_t view_bits;          /* ones over all p x p views the expansion of f^k reads:
+                                   sum over all i, j of ones(f_i^k . V_{j,i}); p at level 0 */
     int64_t sieved_bits;        /* sum over i != j of ones(f_i^k . V_{j,i}) */
     int64_t unsieved_bits;      /* (p - 1) * |f^k|: ones the Allgatherv of Alg. 1 carries */
     int64_t raw_bytes;          /* p (p - 1) 8 ceil(|R|/64): Alg. 1 bitmap bytes */
@@ -177,8 +187,8 @@ typedef struct csbfs_level_stats {
     int64_t wah_sieved_bytes;   /* sum over i != j of 8 |WAH(f_i^k . V_{j,i})|: Alg. 3 bytes */
     int64_t self_bytes;         /* sum over i of 8 |WAH(f_i^k . V_{i,i})| (never sent) */
     int64_t max_rank_bytes;     /* max over i of Alg. 3 bytes sent plus received by P_i */
-    float ms_expand;            /* expansion of f^(k-1) that produced f^k (TIMING) */
-    float ms_update;            /* mask, visit update and reduction (TIMING) */
+    float ms_expand;            /* expansion of f^k (both expansion kernels) (TIMING) */
+    float ms_update;            /* mask, visit update and reduction that follow it (TIMING) */
     float ms_compress;          /* sieve + WAH encode of the f^k messages (TIMING) */
     float ms_decode;            /* decode/merge of the f^k messages (TIMING) */
 } csbfs_level_stats;

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcsbfs.so")
 
 OK, EINVAL, ERANGE, ENOSPACE, EHIP, EOVERFLOW, ECORRUPT = 0, -1, -2, -3, -4, -5, -6
-FLAG_TIMING, FLAG_KEEP_STREAMS, FLAG_NO_SIEVE = 1, 2, 4
+FLAG_TIMING, FLAG_KEEP_STREAMS, FLAG_NO_SIEVE, FLAG_SPARSE_ONLY, FLAG_DENSE_ONLY = 1, 2, 4, 8, 16
 
 _lib = None
 
@@ -36,7 +36,7 @@ class GraphInfo(ctypes.Structure):
 
 class LevelStats(ctypes.Structure):
     _fields_ = [("frontier", ctypes.c_int64), ("edges", ctypes.c_int64),
-                ("sieved_bits", ctypes.c_int64), ("unsieved_bits", ctypes.c_int64),
+                ("view_bits", ctypes.c_int64), ("sieved_bits", ctypes.c_int64), ("unsieved_bits", ctypes.c_int64),
                 ("raw_bytes", ctypes.c_int64), ("wah_unsieved_bytes", ctypes.c_int64),
                 ("wah_sieved_bytes", ctypes.c_int64), ("self_bytes", ctypes.c_int64),
                 ("max_rank_bytes", ctypes.c_int64), ("ms_expand", ctypes.c_float),

@@ -1,22 +1,30 @@
 // The level loop of Algorithm 3 (Sec. V.B) over P virtual processors on one
 // GPU. Processor i's state lives in slices of device arrays: visited bits
-// pi_i and frontier piece f_i (R bits each), the temporary t_i, and its P
-// incoming frontier pieces f_{i,j}, the "views" (bits of R_j as received from
-// P_j). One level k:
+// pi_i and frontier piece f_i (R bits each), the "seen" bits S_i (pi_i plus
+// the vertices discovered during the current level), and its P incoming
+// frontier pieces f_{i,j}, the "views" (bits of R_j as received from P_j).
+// One level k:
 //
-//   expand   t_i = sum_j A_{i,j} (x) f_{i,j} over the (select, max) semiring,
-//            top-down: every set bit u of a view is a source whose row in
-//            block (i, j) is pushed to its targets v; an unvisited v records
-//            u by atomicMax into parent[v] (the highest label wins, Sec.
-//            III.A) and the first writer sets bit v of t_i.
-//   update   t_i &= ~pi_i; pi_i |= t_i; f_i = t_i; level[v] = k + 1; the
-//            frontier size is reduced into a counter that the host reads.
+//   expand   t_i = sum_j A_{i,j} (x) f_{i,j} over the (select, max) semiring
+//            (Sec. III.A: the highest-labelled frontier neighbour wins).
+//            Top-down: every set bit u of view (i, j) is a source whose row
+//            in block (i, j) is pushed to its targets v in R_i. Two exact
+//            evaluations of the same product, chosen per level:
+//              sparse: an unvisited v takes u by atomicMax into parent[v],
+//                      the first writer sets S bit v;
+//              dense:  the push only sets S bits (a bitmap small enough to
+//                      stay in L2); then every new v pulls its parent: the
+//                      rows of v are sorted by decreasing id, so the first
+//                      neighbour found in the views is the maximum.
+//   update   t_i = S_i & ~pi_i; pi_i = S_i; f_i = t_i; level[v] = k + 1; the
+//            frontier size is reduced into a counter that the host reads;
+//            the views are cleared for the next level's messages.
 //   sieve + compress   stream i -> j = WAH-64(f_i AND V_{j,i})  (wah.hip)
 //   exchange           stream slot (i, j) is P_j's receive buffer from P_i
 //   decode/merge       view (j, i) |= WAH^-1(stream i -> j)    (wah.hip)
 //
-// The expansion reads each view word once and clears it, so the views are
-// zero again when the decoder ORs the next level's messages into them.
+// Processor i's pull reads the row of v in A_{i,j}; by the symmetry of A it
+// is the same array as the column of v in A_{j,i}, block (j, i)'s storage.
 #include <vector>
 
 #include "graph.hpp"
@@ -26,6 +34,8 @@ namespace {
 
 constexpr int kExpThreads = 256;
 constexpr int kUpdThreads = 256;
+constexpr int kPullThreads = 256;
+constexpr int kPullRounds = 16;  // per-lane steps (kUnroll entries each) before the wave helps
 constexpr int kEvPerLevel = 5;
 
 struct BigItem {
@@ -36,23 +46,25 @@ struct BigItem {
 };
 
 struct ExpandArgs {
-    uint64_t *view;
-    int64_t view_words;
+    const uint64_t *view;
+    int64_t rank_words;        // view words per processor: P * W
     const int32_t *row_ptr;
     const int64_t *col_base;
     const uint32_t *col;
     const uint64_t *pi;
+    uint64_t *S;
     int32_t *parent;
-    uint64_t *T;
     BigItem *queue;
-    uint32_t *queue_count;
-    int64_t queue_cap;
+    const int64_t *qoff;       // [P + 1]: processor r's chunk queue is queue[qoff[r], qoff[r+1])
+    uint32_t *queue_count;     // [P] items pushed
+    int32_t tile_words;        // view words per tile (<= 64)
     int64_t R;
     int64_t W;
     int32_t P;
     unsigned long long *edges;
     int32_t *status;
 };
+
 
 __device__ __forceinline__ int wave_incl_scan_i32(int v) {
     const int lane = threadIdx.x & 63;
@@ -64,131 +76,398 @@ __device__ __forceinline__ int wave_incl_scan_i32(int v) {
     return v;
 }
 
-// Record source u for target v (global ids) if v is not yet visited.
-__device__ __forceinline__ void relax(const ExpandArgs &a, int64_t v, int32_t u) {
-    const uint64_t bit = 1ull << (v & 63);
-    if (a.pi[v >> 6] & bit) return;
-    const int32_t old = __hip_atomic_load(&a.parent[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old >= u) return;
-    atomicMax(&a.parent[v], u);
-    if (old < 0) atomicOr((unsigned long long *)&a.T[v >> 6], (unsigned long long)bit);
+// Owner lane of slot x: the largest lane L whose exclusive prefix excl[L] is
+// at most x (excl non-decreasing over the lanes, excl[0] = 0).
+__device__ __forceinline__ int owner_lane(int32_t excl, int32_t x) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int probe = lo + step;
+        const int32_t ex = __shfl(excl, probe < 64 ? probe : 63, 64);
+        if (probe < 64 && ex <= x) lo = probe;
+    }
+    return lo;
 }
 
+// Position of the r-th (0-based) set bit of w; w has more than r set bits.
+__device__ __forceinline__ int select_bit(uint64_t w, int r) {
+    int pos = 0;
+    int c = __popc((uint32_t)w);
+    if (r >= c) {
+        r -= c;
+        w >>= 32;
+        pos += 32;
+    }
+    uint32_t x = (uint32_t)w;
+    c = __popc(x & 0xFFFFu);
+    if (r >= c) {
+        r -= c;
+        x >>= 16;
+        pos += 16;
+    }
+    c = __popc(x & 0xFFu);
+    if (r >= c) {
+        r -= c;
+        x >>= 8;
+        pos += 8;
+    }
+    c = __popc(x & 0xFu);
+    if (r >= c) {
+        r -= c;
+        x >>= 4;
+        pos += 4;
+    }
+    c = __popc(x & 0x3u);
+    if (r >= c) {
+        r -= c;
+        x >>= 2;
+        pos += 2;
+    }
+    if (r >= (int)(x & 1u)) pos += 1;
+    return pos;
+}
+
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
+    const int32_t lo = __shfl((int32_t)(uint32_t)v, src, 64);
+    const int32_t hi = __shfl((int32_t)(v >> 32), src, 64);
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+constexpr int kUnroll = 4;  // independent edges in flight per lane
+
+// Relax kUnroll (target v, source u) pairs; every load is issued before any
+// result is used, so their latencies overlap.
+//   sparse: an unvisited v takes u by atomicMax into parent[v] (the update
+//           finds the new vertices as the unvisited ones with a parent).
+//   dense:  v is only marked seen.
+template <bool kDense>
+__device__ __forceinline__ void relax_batch(const ExpandArgs &a, const int64_t (&v)[kUnroll],
+                                            const int32_t (&u)[kUnroll], const bool (&ok)[kUnroll]) {
+    if (kDense) {
+        uint64_t w[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k)
+            w[k] = ok[k] ? __hip_atomic_load(&a.S[v[k] >> 6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                         : ~0ull;
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            const uint64_t bit = 1ull << (v[k] & 63);
+            if (!(w[k] & bit)) atomicOr((unsigned long long *)&a.S[v[k] >> 6], (unsigned long long)bit);
+        }
+    } else {
+        uint64_t pw[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) pw[k] = ok[k] ? a.pi[v[k] >> 6] : ~0ull;
+        int32_t old[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+            const bool need = !((pw[k] >> (v[k] & 63)) & 1);
+            old[k] = need ? __hip_atomic_load(&a.parent[v[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                          : INT32_MAX;
+        }
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k)
+            if (old[k] < u[k]) atomicMax(&a.parent[v[k]], u[k]);
+    }
+}
+
+// A wavefront takes 64 view words at a time (lane = word). Their set bits
+// are ranked across the tile and taken 64 at a time (lane = source u). Rows
+// longer than kBigRow go to the chunk queue (one wave-aggregated
+// reservation); the remaining edges of the 64 sources are spread evenly over
+// the lanes, kUnroll edges per lane per step.
+template <bool kDense>
+__device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int64_t tile,
+                                            unsigned long long &edges) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wl = tile * a.tile_words + lane;
+    const bool in = lane < a.tile_words && wl < a.rank_words;
+    const int64_t w0 = (int64_t)r * a.rank_words + tile * a.tile_words;  // word of lane 0
+    const uint64_t bits = in ? a.view[w0 + lane] : 0;
+    const int cnt = __popcll(bits);
+    const int incl_b = wave_incl_scan_i32(cnt);
+    const int tot_b = __shfl(incl_b, 63, 64);
+    const int excl_b = incl_b - cnt;
+    uint32_t *qcount = a.queue_count + r;
+    BigItem *queue = a.queue + a.qoff[r];
+    const int64_t qcap = a.qoff[r + 1] - a.qoff[r];
+    for (int base = 0; base < tot_b; base += 64) {
+        const int rk = base + lane;
+        const int L = owner_lane(excl_b, rk < tot_b ? rk : tot_b - 1);
+        const uint64_t wb = __shfl(bits, L, 64);
+        const int rr = rk - __shfl(excl_b, L, 64);
+        int32_t rs = 0, deg = 0, u = 0;
+        int64_t b = 0, ul = 0, gstart = 0;
+        if (rk < tot_b) {
+            const int64_t wi = w0 + L;
+            b = wi / a.W;
+            const int64_t q = wi - b * a.W;
+            const int32_t j = (int32_t)(b - (int64_t)r * a.P);
+            ul = (q << 6) + select_bit(wb, rr);
+            const int32_t *rp = a.row_ptr + b * (a.R + 1) + ul;
+            rs = rp[0];
+            deg = rp[1] - rs;
+            gstart = a.col_base[b] + rs;
+            u = (int32_t)(j * a.R + ul);
+        }
+        const int32_t items = deg > kBigRow ? (deg + kBigChunk - 1) / kBigChunk : 0;
+        const int32_t items_incl = wave_incl_scan_i32(items);
+        const int32_t items_total = __shfl(items_incl, 63, 64);
+        if (items_total) {
+            uint32_t qbase = 0;
+            if (lane == 63) qbase = atomicAdd(qcount, (uint32_t)items_total);
+            qbase = __shfl(qbase, 63, 64);
+            if (items) {
+                const int64_t pos = (int64_t)qbase + items_incl - items;
+                if (pos + items > qcap) {
+                    *a.status = 2;  // cannot happen: the capacity bounds every row at once
+                } else {
+                    for (int32_t c = 0; c < items; ++c) {
+                        BigItem it;
+                        it.block = (int32_t)b;
+                        it.u_local = (int32_t)ul;
+                        it.start = rs + c * kBigChunk;
+                        it.end = min(rs + deg, rs + (c + 1) * kBigChunk);
+                        queue[pos + c] = it;
+                    }
+                }
+                deg = 0;
+            }
+        }
+        const int32_t incl = wave_incl_scan_i32(deg);
+        const int32_t total = __shfl(incl, 63, 64);
+        const int32_t excl = incl - deg;
+        edges += (unsigned long long)total;
+        const int64_t vbase = (int64_t)r * a.R;
+        for (int32_t e0 = 0; e0 < total; e0 += 64 * kUnroll) {
+            int64_t v[kUnroll];
+            int32_t uu[kUnroll];
+            bool ok[kUnroll];
+            uint32_t c[kUnroll];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                const int32_t e = e0 + 64 * k + lane;
+                ok[k] = e < total;
+                const int o = owner_lane(excl, ok[k] ? e : total - 1);
+                const int64_t gs = shfl64(gstart, o);
+                const int32_t ex = __shfl(excl, o, 64);
+                uu[k] = __shfl(u, o, 64);
+                c[k] = ok[k] ? a.col[gs + (e - ex)] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) v[k] = vbase + c[k];
+            relax_batch<kDense>(a, v, uu, ok);
+        }
+    }
+}
+
+// A wavefront takes tiles of tile_words view words (lane = word), strided
+// over the grid. The set bits of a tile are ranked and taken 64 at a time
+// (lane = source u). Rows longer than kBigRow go to the processor's chunk
+// queue (one wave-aggregated reservation); the remaining edges of the 64
+// sources are spread evenly over the lanes, kUnroll edges per lane per step.
+template <bool kDense>
 __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t ntiles = (a.view_words + 63) >> 6;
+    const int64_t ntiles = (a.rank_words + a.tile_words - 1) / a.tile_words;
     unsigned long long edges = 0;
-    for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
-        const int64_t w = (tile << 6) + lane;
-        uint64_t bits = w < a.view_words ? a.view[w] : 0;
-        if (bits) a.view[w] = 0;
-        uint64_t nz = __ballot(bits != 0);
-        while (nz) {
-            const int src = __ffsll((unsigned long long)nz) - 1;
-            nz &= nz - 1;
-            const uint64_t wb = __shfl(bits, src, 64);
-            const int64_t wi = (tile << 6) + src;
-            const int64_t b = wi / a.W;
-            const int64_t q = wi - b * a.W;
-            const int32_t i = (int32_t)(b / a.P);
-            const int32_t j = (int32_t)(b - (int64_t)i * a.P);
-            const int64_t ul = (q << 6) + lane;
-            int32_t rs = 0, deg = 0;
-            if ((wb >> lane) & 1) {
-                const int32_t *rp = a.row_ptr + b * (a.R + 1) + ul;
-                rs = rp[0];
-                deg = rp[1] - rs;
-            }
-            // long rows go to the chunk queue, one wave-aggregated reservation
-            int32_t items = deg > kBigRow ? (deg + kBigChunk - 1) / kBigChunk : 0;
-            const int32_t items_incl = wave_incl_scan_i32(items);
-            const int32_t items_total = __shfl(items_incl, 63, 64);
-            if (items_total) {
-                uint32_t base = 0;
-                if (lane == 63) base = atomicAdd(a.queue_count, (uint32_t)items_total);
-                base = __shfl(base, 63, 64);
-                if (items) {
-                    int64_t pos = (int64_t)base + items_incl - items;
-                    if (pos + items > a.queue_cap) {
-                        *a.status = 2;  // cannot happen: the capacity bounds every row at once
-                    } else {
-                        for (int32_t c = 0; c < items; ++c) {
-                            BigItem it;
-                            it.block = (int32_t)b;
-                            it.u_local = (int32_t)ul;
-                            it.start = rs + c * kBigChunk;
-                            it.end = min(rs + deg, rs + (c + 1) * kBigChunk);
-                            a.queue[pos + c] = it;
-                        }
-                    }
-                    deg = 0;
-                }
-            }
-            const int32_t incl = wave_incl_scan_i32(deg);
-            const int32_t total = __shfl(incl, 63, 64);
-            const int32_t excl = incl - deg;
-            edges += (unsigned long long)total;
-            const int32_t u_base = (int32_t)(j * a.R + (q << 6));
-            const uint32_t *colb = a.col + a.col_base[b];
-            const int64_t vbase = (int64_t)i * a.R;
-            for (int32_t e0 = 0; e0 < total; e0 += 64) {
-                const int32_t e = e0 + lane;
-                // owner: the largest lane L with excl[L] <= e
-                int lo = 0;
-#pragma unroll
-                for (int step = 32; step > 0; step >>= 1) {
-                    const int probe = lo + step;
-                    const int32_t ex = __shfl(excl, probe < 64 ? probe : 63, 64);
-                    if (probe < 64 && ex <= e) lo = probe;
-                }
-                const int32_t ex_lo = __shfl(excl, lo, 64);
-                const int32_t rs_lo = __shfl(rs, lo, 64);
-                if (e < total) {
-                    const uint32_t vl = colb[rs_lo + (e - ex_lo)];
-                    relax(a, vbase + vl, u_base + lo);
-                }
-            }
-        }
+    for (int64_t gt = wave; gt < ntiles * a.P; gt += nwaves) {
+        const int32_t r = (int32_t)(gt / ntiles);
+        expand_tile<kDense>(a, r, gt - (int64_t)r * ntiles, edges);
     }
     // `total` is wave-uniform, so every lane holds the wave's edge count
     if (lane == 0 && edges) atomicAdd(a.edges, edges);
 }
 
+// Chunk-queue items (<= kBigChunk entries of one long row) of every
+// processor, strided over the grid.
+template <bool kDense>
 __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t queued = *a.queue_count;
-    const int64_t count = queued < a.queue_cap ? queued : a.queue_cap;
     unsigned long long edges = 0;
-    for (int64_t k = wave; k < count; k += nwaves) {
-        const BigItem it = a.queue[k];
-        const int64_t b = it.block;
-        const int32_t i = (int32_t)(b / a.P);
-        const int32_t j = (int32_t)(b - (int64_t)i * a.P);
-        const int32_t u = (int32_t)(j * a.R + it.u_local);
-        const uint32_t *colb = a.col + a.col_base[b];
-        const int64_t vbase = (int64_t)i * a.R;
-        for (int32_t e = it.start + lane; e < it.end; e += 64) relax(a, vbase + colb[e], u);
-        edges += (unsigned long long)(it.end - it.start);
+    int64_t before = 0;  // items of the processors before r, for a grid-wide stride
+    for (int32_t r = 0; r < a.P; ++r) {
+        const int64_t cap = a.qoff[r + 1] - a.qoff[r];
+        const int64_t queued = a.queue_count[r];
+        const int64_t count = queued < cap ? queued : cap;
+        const BigItem *queue = a.queue + a.qoff[r];
+        const int64_t vbase = (int64_t)r * a.R;
+        int64_t first = (wave - before) % nwaves;
+        if (first < 0) first += nwaves;
+        before += count;
+        for (int64_t kk = first; kk < count; kk += nwaves) {
+            const BigItem it = queue[kk];
+            const int64_t b = it.block;
+            const int32_t j = (int32_t)(b - (int64_t)r * a.P);
+            const int32_t u = (int32_t)(j * a.R + it.u_local);
+            const uint32_t *colb = a.col + a.col_base[b];
+            for (int32_t e0 = it.start; e0 < it.end; e0 += 64 * kUnroll) {
+                int64_t v[kUnroll];
+                int32_t uu[kUnroll];
+                bool ok[kUnroll];
+#pragma unroll
+                for (int k = 0; k < kUnroll; ++k) {
+                    const int32_t e = e0 + 64 * k + lane;
+                    ok[k] = e < it.end;
+                    v[k] = vbase + (ok[k] ? colb[e] : 0u);
+                    uu[k] = u;
+                }
+                relax_batch<kDense>(a, v, uu, ok);
+            }
+            edges += (unsigned long long)(it.end - it.start);
+        }
     }
     if (lane == 0 && edges) atomicAdd(a.edges, edges);
 }
 
+struct PullArgs {
+    const uint64_t *S;
+    const uint64_t *pi;
+    const uint64_t *view;
+    const int32_t *row_ptr;
+    const int64_t *col_base;
+    const uint32_t *col;
+    int32_t *parent;
+    int64_t words;  // n / 64
+    int64_t R;
+    int64_t W;
+    int32_t P;
+    int32_t *status;
+};
+
+// Dense evaluation, second half: parent[v] for every vertex v discovered in
+// this level (S & ~pi). A wavefront takes 64 words at a time and ranks their
+// new vertices, 64 at a time (lane = v). Each lane walks the rows of v from
+// block j = P-1 down to 0, each row in decreasing id order, kUnroll entries
+// per step, and stops at the first source found in its views. Lanes still
+// searching after kPullRounds steps are finished by the whole wave, 64
+// entries per step.
+__global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t ntiles = (a.words + 63) >> 6;
+    for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
+        const int64_t wq = (tile << 6) + lane;
+        const uint64_t t = wq < a.words ? (a.S[wq] & ~a.pi[wq]) : 0;
+        const int cnt = __popcll(t);
+        const int incl_b = wave_incl_scan_i32(cnt);
+        const int tot_b = __shfl(incl_b, 63, 64);
+        const int excl_b = incl_b - cnt;
+        for (int base = 0; base < tot_b; base += 64) {
+            const int r = base + lane;
+            const int L = owner_lane(excl_b, r < tot_b ? r : tot_b - 1);
+            const uint64_t tw = __shfl(t, L, 64);
+            const int rr = r - __shfl(excl_b, L, 64);
+            const bool mine = r < tot_b;
+            int32_t i = 0;
+            int64_t vl = 0;
+            int32_t j = a.P - 1, e = 0, re = 0;
+            int32_t found = -1;
+            if (mine) {
+                const int64_t qq = (tile << 6) + L;
+                i = (int32_t)(qq / a.W);
+                vl = ((qq - (int64_t)i * a.W) << 6) + select_bit(tw, rr);
+                const int32_t *rp = a.row_ptr + ((int64_t)j * a.P + i) * (a.R + 1) + vl;
+                e = rp[0];
+                re = rp[1];
+            }
+            const uint64_t *vw = a.view + (int64_t)i * a.P * a.W;  // views (i, *)
+            bool busy = mine;
+            for (int round = 0; round < kPullRounds; ++round) {
+                if (busy) {
+                    while (e == re && j > 0) {
+                        --j;
+                        const int32_t *rp = a.row_ptr + ((int64_t)j * a.P + i) * (a.R + 1) + vl;
+                        e = rp[0];
+                        re = rp[1];
+                    }
+                    if (e == re) {
+                        busy = false;  // no frontier neighbour: impossible for a seen vertex
+                    } else {
+                        const int32_t nk = re - e < kUnroll ? re - e : kUnroll;
+                        const uint32_t *cp = a.col + a.col_base[(int64_t)j * a.P + i] + e;
+                        uint32_t c[kUnroll];
+                        uint64_t x[kUnroll];
+#pragma unroll
+                        for (int k = 0; k < kUnroll; ++k) c[k] = k < nk ? cp[k] : 0u;
+#pragma unroll
+                        for (int k = 0; k < kUnroll; ++k)
+                            x[k] = k < nk ? vw[(int64_t)j * a.W + (c[k] >> 6)] : 0ull;
+#pragma unroll
+                        for (int k = kUnroll - 1; k >= 0; --k)
+                            if ((x[k] >> (c[k] & 63)) & 1) found = (int32_t)(j * a.R + c[k]);
+                        if (found >= 0) busy = false;
+                        e += nk;
+                    }
+                }
+                if (!__ballot(busy)) break;
+            }
+            uint64_t slow = __ballot(busy);
+            while (slow) {
+                const int Ls = __ffsll((unsigned long long)slow) - 1;
+                slow &= slow - 1;
+                int32_t jj = __shfl(j, Ls, 64);
+                int32_t ee = __shfl(e, Ls, 64);
+                int32_t rr2 = __shfl(re, Ls, 64);
+                const int32_t ii = __shfl(i, Ls, 64);
+                const int64_t vll = shfl64(vl, Ls);
+                const uint64_t *vws = a.view + (int64_t)ii * a.P * a.W;
+                int32_t got = -1;
+                for (;;) {
+                    if (ee >= rr2) {
+                        if (jj == 0) break;
+                        --jj;
+                        const int32_t *rp = a.row_ptr + ((int64_t)jj * a.P + ii) * (a.R + 1) + vll;
+                        ee = rp[0];
+                        rr2 = rp[1];
+                        continue;
+                    }
+                    const int32_t pos = ee + lane;
+                    bool hit = false;
+                    uint32_t ul = 0;
+                    if (pos < rr2) {
+                        ul = a.col[a.col_base[(int64_t)jj * a.P + ii] + pos];
+                        hit = (vws[(int64_t)jj * a.W + (ul >> 6)] >> (ul & 63)) & 1;
+                    }
+                    const uint64_t hits = __ballot(hit);
+                    if (hits) {
+                        const int first = __ffsll((unsigned long long)hits) - 1;
+                        got = (int32_t)(jj * a.R + __shfl(ul, first, 64));
+                        break;
+                    }
+                    ee += 64;
+                }
+                if (lane == Ls) found = got;
+            }
+            if (mine) {
+                if (found >= 0)
+                    a.parent[(int64_t)i * a.R + vl] = found;
+                else
+                    *a.status = 3;
+            }
+        }
+    }
+}
+
 struct UpdateArgs {
-    uint64_t *T;
+    const int32_t *parent;
+    uint64_t *S;
     uint64_t *pi;
     uint64_t *f;
+    uint64_t *view;
     int32_t *level;
     int32_t next_level;
-    int64_t words;        // n / 64
-    int64_t W;            // words per processor
+    int64_t words;  // n / 64
+    int64_t W;      // words per processor
     int32_t P;
     unsigned long long *rank_count;  // [P]
-    unsigned long long *total;       // [1]
-    uint32_t *queue_count;
+    unsigned long long *total;       // [1]: frontier size
+    uint32_t *ctrs;                  // [P]: chunk-queue counts, reset for the next level
 };
 
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
@@ -196,17 +475,28 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     uint64_t t = 0;
     if (q < a.words) {
-        t = a.T[q];
-        if (t) {
-            a.T[q] = 0;
-            const uint64_t p = a.pi[q];
+        const uint64_t p = a.pi[q];
+        if (~p) {
+            // the new vertices of this word: unvisited ones that got a parent
+            const int4 *pp = reinterpret_cast<const int4 *>(a.parent + (q << 6));
+#pragma unroll 4
+            for (int k = 0; k < 16; ++k) {
+                const int4 x = pp[k];
+                t |= (uint64_t)(x.x >= 0) << (4 * k) | (uint64_t)(x.y >= 0) << (4 * k + 1) |
+                     (uint64_t)(x.z >= 0) << (4 * k + 2) | (uint64_t)(x.w >= 0) << (4 * k + 3);
+            }
             t &= ~p;
+        }
+        if (t) {
             a.pi[q] = p | t;
+            a.S[q] = p | t;
         }
         a.f[q] = t;
+        // clear processor i's views (i, j) at the same offset for every j
+        const int64_t i = q / a.W, ql = q - i * a.W;
+        for (int32_t j = 0; j < a.P; ++j) a.view[(i * a.P + j) * a.W + ql] = 0;
     }
-    if (q == 0) *a.queue_count = 0;
-    // frontier size per processor
+    if (q < a.P) a.ctrs[q] = 0;
     const int c = __popcll(t);
     const int64_t q0 = __shfl(q, 0, 64);
     const int64_t q63 = q0 + 63 < a.words ? q0 + 63 : a.words - 1;
@@ -215,11 +505,11 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
         for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
         if (lane == 0 && s && q0 < a.words) {
             atomicAdd(&a.rank_count[q0 / a.W], (unsigned long long)s);
-            atomicAdd(a.total, (unsigned long long)s);
+            atomicAdd(&a.total[0], (unsigned long long)s);
         }
     } else if (c) {
         atomicAdd(&a.rank_count[q / a.W], (unsigned long long)c);
-        atomicAdd(a.total, (unsigned long long)c);
+        atomicAdd(&a.total[0], (unsigned long long)c);
     }
     // level of every new vertex, one coalesced row of 64 per non-zero word
     uint64_t nz = __ballot(t != 0);
@@ -227,8 +517,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
         const int src = __ffsll((unsigned long long)nz) - 1;
         nz &= nz - 1;
         const uint64_t tw = __shfl(t, src, 64);
-        const int64_t qq = q0 + src;
-        if ((tw >> lane) & 1) a.level[(qq << 6) + lane] = a.next_level;
+        if ((tw >> lane) & 1) a.level[((q0 + src) << 6) + lane] = a.next_level;
     }
 }
 
@@ -236,7 +525,7 @@ struct SeedArgs {
     int32_t *level;
     int32_t *parent;
     uint64_t *pi;
-    uint64_t *T;
+    uint64_t *S;
     uint64_t *view;
     int64_t n;
     int64_t words;
@@ -245,29 +534,30 @@ struct SeedArgs {
 
 __global__ void seed_fill_kernel(SeedArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < a.n; k += stride) {
-        a.level[k] = -1;
-        a.parent[k] = -1;
+    const int64_t top = a.n > a.view_words ? a.n : a.view_words;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < top; k += stride) {
+        if (k < a.n) {
+            a.level[k] = -1;
+            a.parent[k] = -1;
+        }
         if (k < a.words) {
             a.pi[k] = 0;
-            a.T[k] = 0;
+            a.S[k] = 0;
         }
         if (k < a.view_words) a.view[k] = 0;
     }
-    for (int64_t k = a.n + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < a.view_words;
-         k += stride)
-        a.view[k] = 0;
 }
 
 // f(s) <- s: the source is known to every processor without a message.
 __global__ void seed_root_kernel(SeedArgs a, int64_t root, int64_t R, int64_t W, int32_t P,
-                                 unsigned long long *frontier0, unsigned long long *rank0) {
+                                 unsigned long long *ctl0, unsigned long long *rank0) {
     const int64_t own = root / R, rl = root - own * R;
     a.level[root] = 0;
     a.parent[root] = (int32_t)root;
     a.pi[root >> 6] |= 1ull << (root & 63);
+    a.S[root >> 6] |= 1ull << (root & 63);
     for (int32_t i = 0; i < P; ++i) a.view[((int64_t)i * P + own) * W + (rl >> 6)] |= 1ull << (rl & 63);
-    *frontier0 = 1;
+    ctl0[0] = 1;
     rank0[own] = 1;
 }
 
@@ -286,12 +576,12 @@ using namespace csbfs;
 // Per-level device counters, slot k for k < L and slot L for levels past the
 // engine's capacity (reset before each use).
 struct LevelCounters {
-    unsigned long long *frontier;   // [L+1]
-    unsigned long long *rank;       // [L+1][P]
-    unsigned long long *edges;      // [L+1]
-    unsigned long long *sbits;      // [L+1][S]
-    unsigned long long *uwords;     // [L+1][P]
-    int64_t *words;                 // [L+1][S]
+    unsigned long long *ctl;     // [L+1][2]: |f^k|, sum of degrees over f^k
+    unsigned long long *rank;    // [L+1][P]
+    unsigned long long *edges;   // [L+1]
+    unsigned long long *sbits;   // [L+1][S]
+    unsigned long long *uwords;  // [L+1][P]
+    int64_t *words;              // [L+1][S]
 };
 
 struct csbfs_engine {
@@ -300,19 +590,23 @@ struct csbfs_engine {
     int32_t L = 0;
     uint32_t flags = 0;
     int64_t S = 0, cap = 0, nseg = 0, nchunk = 0;
-    uint64_t *pi = nullptr, *f = nullptr, *T = nullptr, *view = nullptr, *arena = nullptr;
+    uint64_t *pi = nullptr, *f = nullptr, *seen = nullptr, *view = nullptr, *arena = nullptr;
     int32_t *seg_count = nullptr, *seg_first = nullptr;
     int64_t *chunk_groups = nullptr;
     BigItem *queue = nullptr;
-    uint32_t *queue_count = nullptr;
+    uint32_t *ctrs = nullptr;     // [P]: chunk-queue items pushed
+    int64_t *qoff = nullptr;      // [P + 1] chunk queue regions
     int64_t queue_cap = 0;
     void *counters_mem = nullptr;
     size_t counters_bytes = 0;
     LevelCounters lc{};
     int32_t *status = nullptr;
-    unsigned long long *host_count = nullptr;  // pinned
+    unsigned long long *host_ctl = nullptr;  // pinned [2]
     std::vector<hipEvent_t> events;
     int32_t last_levels = 0;
+    // The dense evaluation is used only when asked for: measured on R-MAT
+    // graphs, the atomicMax push is faster at every level.
+    bool dense_default = false;
     std::vector<void *> allocs;
 };
 
@@ -328,8 +622,9 @@ void engine_release(csbfs_engine *e) {
     (void)hipDeviceSynchronize();
     for (void *p : e->allocs) (void)hipFree(p);
     e->allocs.clear();
-    if (e->host_count) (void)hipHostFree(e->host_count);
-    for (hipEvent_t ev : e->events) (void)hipEventDestroy(ev);
+    if (e->host_ctl) (void)hipHostFree(e->host_ctl);
+    for (hipEvent_t ev : e->events)
+        if (ev) (void)hipEventDestroy(ev);
     e->events.clear();
     delete e;
 }
@@ -343,8 +638,11 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     if (!g) return fail(CSBFS_EINVAL, "csbfs_engine_create: graph is NULL");
     if (max_levels < 1 || max_levels > 65536)
         return fail(CSBFS_EINVAL, "csbfs_engine_create: max_levels outside [1, 65536]");
-    if (flags & ~(CSBFS_FLAG_TIMING | CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE))
+    if (flags & ~(CSBFS_FLAG_TIMING | CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE |
+                  CSBFS_FLAG_SPARSE_ONLY | CSBFS_FLAG_DENSE_ONLY))
         return fail(CSBFS_EINVAL, "csbfs_engine_create: unknown flag");
+    if ((flags & CSBFS_FLAG_SPARSE_ONLY) && (flags & CSBFS_FLAG_DENSE_ONLY))
+        return fail(CSBFS_EINVAL, "csbfs_engine_create: SPARSE_ONLY and DENSE_ONLY exclude each other");
     int rc = graph_device_check(g);
     if (rc) return rc;
     csbfs_engine *e = new csbfs_engine();
@@ -359,7 +657,9 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     e->nchunk = dec_chunks(g->R);
     const int64_t words = n / 64;
     const int64_t arena_slots = (flags & CSBFS_FLAG_KEEP_STREAMS) ? (int64_t)max_levels + 1 : 1;
-    e->queue_cap = g->big_items > 0 ? g->big_items : 1;
+    std::vector<int64_t> qoff(P + 1, 0);
+    for (int64_t r = 0; r < P; ++r) qoff[r + 1] = qoff[r] + g->big_items[r];
+    e->queue_cap = qoff[P] > 0 ? qoff[P] : 1;
 #define ALLOC(ptr, bytes)                                                  \
     do {                                                                   \
         void *_p = nullptr;                                                \
@@ -372,24 +672,25 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     } while (0)
     ALLOC(e->pi, sizeof(uint64_t) * words);
     ALLOC(e->f, sizeof(uint64_t) * words);
-    ALLOC(e->T, sizeof(uint64_t) * words);
+    ALLOC(e->seen, sizeof(uint64_t) * words);
     ALLOC(e->view, sizeof(uint64_t) * P * words);
     ALLOC(e->arena, sizeof(uint64_t) * e->S * e->cap * arena_slots);
     ALLOC(e->seg_count, sizeof(int32_t) * e->S * e->nseg);
     ALLOC(e->seg_first, sizeof(int32_t) * e->S * e->nseg);
     ALLOC(e->chunk_groups, sizeof(int64_t) * e->S * e->nchunk);
     ALLOC(e->queue, sizeof(BigItem) * e->queue_cap);
-    ALLOC(e->queue_count, sizeof(uint32_t));
+    ALLOC(e->ctrs, sizeof(uint32_t) * P);
+    ALLOC(e->qoff, sizeof(int64_t) * (P + 1));
     ALLOC(e->status, sizeof(int32_t));
     const int64_t slots = (int64_t)max_levels + 1;
-    const size_t cnt_bytes = sizeof(unsigned long long) * slots * (1 + P + 1 + e->S + P) +
+    const size_t cnt_bytes = sizeof(unsigned long long) * slots * (2 + P + 1 + e->S + P) +
                              sizeof(int64_t) * slots * e->S;
     ALLOC(e->counters_mem, cnt_bytes);
 #undef ALLOC
     e->counters_bytes = cnt_bytes;
     unsigned long long *c = (unsigned long long *)e->counters_mem;
-    e->lc.frontier = c;
-    c += slots;
+    e->lc.ctl = c;
+    c += slots * 2;
     e->lc.rank = c;
     c += slots * P;
     e->lc.edges = c;
@@ -399,14 +700,19 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     e->lc.uwords = c;
     c += slots * P;
     e->lc.words = (int64_t *)c;
-    hipError_t herr = hipHostMalloc((void **)&e->host_count, sizeof(unsigned long long));
+    hipError_t herr = hipMemcpy(e->qoff, qoff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice);
     if (herr != hipSuccess) {
-        e->host_count = nullptr;
+        engine_release(e);
+        return hip_fail(herr, "hipMemcpy(qoff)", __FILE__, __LINE__);
+    }
+    herr = hipHostMalloc((void **)&e->host_ctl, 2 * sizeof(unsigned long long));
+    if (herr != hipSuccess) {
+        e->host_ctl = nullptr;
         engine_release(e);
         return hip_fail(herr, "hipHostMalloc", __FILE__, __LINE__);
     }
     if (flags & CSBFS_FLAG_TIMING) {
-        e->events.resize((size_t)max_levels * kEvPerLevel);
+        e->events.assign((size_t)max_levels * kEvPerLevel, nullptr);
         for (auto &ev : e->events) {
             herr = hipEventCreate(&ev);
             if (herr != hipSuccess) {
@@ -428,15 +734,11 @@ extern "C" int csbfs_engine_free(csbfs_engine *e) {
 
 namespace {
 
-struct LevelPtrs {
-    int64_t slot;
-};
-
 inline int64_t slot_of(const csbfs_engine *e, int64_t k) { return k < e->L ? k : e->L; }
 
 int reset_overflow_slot(csbfs_engine *e, hipStream_t st) {
     const int64_t L = e->L, P = e->g->P, S = e->S;
-    CSBFS_HIP(hipMemsetAsync(e->lc.frontier + L, 0, sizeof(unsigned long long), st));
+    CSBFS_HIP(hipMemsetAsync(e->lc.ctl + 2 * L, 0, 2 * sizeof(unsigned long long), st));
     CSBFS_HIP(hipMemsetAsync(e->lc.rank + L * P, 0, sizeof(unsigned long long) * P, st));
     CSBFS_HIP(hipMemsetAsync(e->lc.edges + L, 0, sizeof(unsigned long long), st));
     CSBFS_HIP(hipMemsetAsync(e->lc.sbits + L * S, 0, sizeof(unsigned long long) * S, st));
@@ -464,33 +766,36 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     // a0: seed
     CSBFS_HIP(hipMemsetAsync(e->counters_mem, 0, e->counters_bytes, st));
     CSBFS_HIP(hipMemsetAsync(e->status, 0, sizeof(int32_t), st));
-    CSBFS_HIP(hipMemsetAsync(e->queue_count, 0, sizeof(uint32_t), st));
-    SeedArgs sa{level, parent, e->pi, e->T, e->view, n, words, view_words};
+    CSBFS_HIP(hipMemsetAsync(e->ctrs, 0, sizeof(uint32_t) * P, st));
+    SeedArgs sa{level, parent, e->pi, e->seen, e->view, n, words, view_words};
     const int64_t fill_items = n > view_words ? n : view_words;
     hipLaunchKernelGGL(seed_fill_kernel, dim3(grid_for(fill_items, 256, 8192)), dim3(256), 0, st, sa);
     CSBFS_HIP(hipGetLastError());
     hipLaunchKernelGGL(seed_root_kernel, dim3(1), dim3(1), 0, st, sa, root, R, W, (int32_t)P,
-                       e->lc.frontier, e->lc.rank);
+                       e->lc.ctl, e->lc.rank);
     CSBFS_HIP(hipGetLastError());
 
     ExpandArgs ea{};
     ea.view = e->view;
-    ea.view_words = view_words;
+    ea.rank_words = P * W;
     ea.row_ptr = g->row_ptr;
     ea.col_base = g->col_base;
     ea.col = g->col;
     ea.pi = e->pi;
+    ea.S = e->seen;
     ea.parent = parent;
-    ea.T = e->T;
     ea.queue = e->queue;
-    ea.queue_count = e->queue_count;
-    ea.queue_cap = e->queue_cap;
+    ea.qoff = e->qoff;
+    ea.queue_count = e->ctrs;
     ea.R = R;
     ea.W = W;
     ea.P = (int32_t)P;
     ea.status = e->status;
-    const unsigned exp_grid = grid_for((view_words + 63) / 64, kExpThreads / 64, 16384);
-    const unsigned big_grid = 2048;
+    PullArgs pa{e->seen, e->pi, e->view, g->row_ptr, g->col_base, g->col, parent, words, R, W,
+                (int32_t)P, e->status};
+    // one resident wave per SIMD slot of every CU, a multiple of the XCD count
+    const unsigned exp_grid = 2048, big_grid = 2048;
+    const unsigned pull_grid = grid_for((words + 63) / 64, kPullThreads / 64, 16384);
     const unsigned upd_grid = grid_for(words, kUpdThreads, 1u << 30);
 
     WahBatch wb{};
@@ -508,6 +813,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     wb.dst_base = e->view;
     wb.status = e->status;
 
+    unsigned long long cur_count = 1;  // |f^k|, read back after each update
     int64_t k = 0;
     for (;; ++k) {
         const int64_t sk = slot_of(e, k), sn = slot_of(e, k + 1);
@@ -515,25 +821,41 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
             rc = reset_overflow_slot(e, st);
             if (rc) return rc;
         }
+        bool dense = e->dense_default;
+        if (e->flags & CSBFS_FLAG_SPARSE_ONLY) dense = false;
+        if (e->flags & CSBFS_FLAG_DENSE_ONLY) dense = true;
         hipEvent_t *ev = (timing && k < e->L) ? &e->events[(size_t)k * kEvPerLevel] : nullptr;
         if (ev) CSBFS_HIP(hipEventRecord(ev[0], st));
-        // a1: expand f^k
+        // a1: expand f^k; small tiles when the frontier is large, so that
+        // every wave gets work, large ones when it is small
+        const bool wide = (double)cur_count * 64.0 >= (double)n;
+        ea.tile_words = wide ? 16 : 64;
         ea.edges = e->lc.edges + sk;
-        hipLaunchKernelGGL(expand_kernel, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
-        CSBFS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(expand_big_kernel, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
-        CSBFS_HIP(hipGetLastError());
+        if (dense) {
+            hipLaunchKernelGGL(expand_kernel<true>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
+            CSBFS_HIP(hipGetLastError());
+            hipLaunchKernelGGL(expand_big_kernel<true>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
+            CSBFS_HIP(hipGetLastError());
+            hipLaunchKernelGGL(pull_kernel, dim3(pull_grid), dim3(kPullThreads), 0, st, pa);
+            CSBFS_HIP(hipGetLastError());
+        } else {
+            hipLaunchKernelGGL(expand_kernel<false>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
+            CSBFS_HIP(hipGetLastError());
+            hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
+            CSBFS_HIP(hipGetLastError());
+        }
         if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
         // a2: mask, visit, f^{k+1}; a3: reduction of |f^{k+1}|
-        UpdateArgs ua{e->T, e->pi, e->f, level, (int32_t)(k + 1), words, W, (int32_t)P,
-                      e->lc.rank + sn * P, e->lc.frontier + sn, e->queue_count};
+        UpdateArgs ua{parent, e->seen, e->pi, e->f, e->view, level, (int32_t)(k + 1), words, W, (int32_t)P, e->lc.rank + sn * P,
+                      e->lc.ctl + 2 * sn, e->ctrs};
         hipLaunchKernelGGL(update_kernel, dim3(upd_grid), dim3(kUpdThreads), 0, st, ua);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
-        CSBFS_HIP(hipMemcpyAsync(e->host_count, e->lc.frontier + sn, sizeof(unsigned long long),
+        CSBFS_HIP(hipMemcpyAsync(e->host_ctl, e->lc.ctl + 2 * sn, 2 * sizeof(unsigned long long),
                                  hipMemcpyDeviceToHost, st));
         CSBFS_HIP(hipStreamSynchronize(st));
-        if (*e->host_count == 0) break;
+        if (e->host_ctl[0] == 0) break;
+        cur_count = e->host_ctl[0];
         // a4 + a5: sieve and compress every stream i -> j
         const int64_t arena_slot = keep ? sn : 0;
         wb.out_base = e->arena + arena_slot * S * e->cap;
@@ -557,15 +879,15 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     CSBFS_HIP(hipMemcpyAsync(&hstatus, e->status, sizeof(hstatus), hipMemcpyDeviceToHost, st));
     const int64_t have = nl < e->L ? nl : e->L;
     const int64_t want = stats_cap < have ? stats_cap : have;
-    std::vector<unsigned long long> fr, rk, ed, sb, uw;
+    std::vector<unsigned long long> ctl, ed, sb, uw;
     std::vector<int64_t> wd;
     if (want > 0) {
-        fr.resize(want);
+        ctl.resize(2 * want);
         ed.resize(want);
         sb.resize(want * S);
         uw.resize(want * P);
         wd.resize(want * S);
-        CSBFS_HIP(hipMemcpyAsync(fr.data(), e->lc.frontier, sizeof(unsigned long long) * want,
+        CSBFS_HIP(hipMemcpyAsync(ctl.data(), e->lc.ctl, sizeof(unsigned long long) * 2 * want,
                                  hipMemcpyDeviceToHost, st));
         CSBFS_HIP(hipMemcpyAsync(ed.data(), e->lc.edges, sizeof(unsigned long long) * want,
                                  hipMemcpyDeviceToHost, st));
@@ -577,14 +899,20 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
                                  hipMemcpyDeviceToHost, st));
     }
     CSBFS_HIP(hipStreamSynchronize(st));
-    if (hstatus != 0) return fail(CSBFS_ECORRUPT, "csbfs_bfs: a stream failed validation while decoding");
+    if (hstatus != 0) {
+        if (hstatus == 1) return fail(CSBFS_ECORRUPT, "csbfs_bfs: a stream failed validation while decoding");
+        return fail(CSBFS_ECORRUPT, "csbfs_bfs: internal consistency check failed");
+    }
     for (int64_t lv = 0; lv < want; ++lv) {
         csbfs_level_stats &s = stats[lv];
         s = csbfs_level_stats{};
-        s.frontier = (int64_t)fr[lv];
+        s.frontier = (int64_t)ctl[2 * lv];
         s.edges = (int64_t)ed[lv];
+        s.view_bits = P;  // the source is set in every view at level 0
         if (lv > 0) {
             int64_t sieved = 0, sent = 0, self = 0, uws = 0, maxr = 0;
+            s.view_bits = 0;
+            for (int64_t q = 0; q < S; ++q) s.view_bits += (int64_t)sb[lv * S + q];
             for (int64_t i = 0; i < P; ++i) {
                 int64_t send = 0, recv = 0;
                 for (int64_t j = 0; j < P; ++j) {

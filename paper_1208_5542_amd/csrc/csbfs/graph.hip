@@ -150,25 +150,30 @@ __global__ void k_directory(const int32_t *row_ptr, int64_t R, int64_t W, int64_
     }
 }
 
-// deg[u] = adjacency entries of u over all blocks of its column; big[0] +=
-// the expansion-queue items the rows of u would need if all were expanded.
+// deg[u] = adjacency entries of u over all blocks of its column; big[i] +=
+// the expansion-queue items that the rows of block-row i would need if every
+// row were expanded at once (the capacity of processor i's chunk queue).
 __global__ void k_degree(const int32_t *row_ptr, int64_t R, int32_t P, int64_t n, int32_t *deg,
                          unsigned long long *big_items) {
-    unsigned long long items = 0;
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = u / R, ul = u - j * R;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = base + threadIdx.x;
+        const bool ok = u < n;
+        const int64_t j = ok ? u / R : 0, ul = ok ? u - j * R : 0;
         int32_t d = 0;
         for (int32_t i = 0; i < P; ++i) {
-            const int32_t *rp = row_ptr + ((int64_t)i * P + j) * (R + 1) + ul;
-            const int32_t len = rp[1] - rp[0];
-            d += len;
-            if (len > kBigRow) items += (len + kBigChunk - 1) / kBigChunk;
+            unsigned long long items = 0;
+            if (ok) {
+                const int32_t *rp = row_ptr + ((int64_t)i * P + j) * (R + 1) + ul;
+                const int32_t len = rp[1] - rp[0];
+                d += len;
+                if (len > kBigRow) items = (len + kBigChunk - 1) / kBigChunk;
+            }
+            for (int s = 32; s > 0; s >>= 1) items += __shfl_xor(items, s, 64);
+            if ((threadIdx.x & 63) == 0 && items) atomicAdd(&big_items[i], items);
         }
-        deg[u] = d;
+        if (ok) deg[u] = d;
     }
-    for (int d = 32; d > 0; d >>= 1) items += __shfl_xor(items, d, 64);
-    if ((threadIdx.x & 63) == 0 && items) atomicAdd(big_items, items);
 }
 
 __global__ void k_count_m(const int32_t *level, const int32_t *deg, int64_t n,
@@ -246,7 +251,7 @@ extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t
     CSBFS_HIP(hipMalloc(&cb.p, sizeof(int64_t) * (B + 1)));
     CSBFS_HIP(hipMalloc(&dir.p, sizeof(uint64_t) * B * W));
     CSBFS_HIP(hipMalloc(&deg.p, sizeof(int32_t) * n));
-    CSBFS_HIP(hipMalloc(&scratch.p, 256));
+    CSBFS_HIP(hipMalloc(&scratch.p, 8 * 64));
     CSBFS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * B * R, st));
     CSBFS_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
 
@@ -289,16 +294,23 @@ extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t
                            (uint32_t *)col.p);
         CSBFS_HIP(hipGetLastError());
     }
+    {
+        uint32_t *c = (uint32_t *)col.p;
+        int src_rc = sort_rows_desc(&c, (const int64_t *)cb.p, (const int32_t *)rp.p, R, p, total, st);
+        col.p = c;
+        if (src_rc) return src_rc;
+    }
     hipLaunchKernelGGL(k_directory, dim3(grid_for(B * W * 64, kThreads)), dim3(kThreads), 0, st,
                        (const int32_t *)rp.p, R, W, B, (uint64_t *)dir.p);
     CSBFS_HIP(hipGetLastError());
-    CSBFS_HIP(hipMemsetAsync(scratch.p, 0, 256, st));
+    CSBFS_HIP(hipMemsetAsync(scratch.p, 0, 8 * 64, st));
     hipLaunchKernelGGL(k_degree, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st,
                        (const int32_t *)rp.p, R, p, n, (int32_t *)deg.p,
                        (unsigned long long *)scratch.p);
     CSBFS_HIP(hipGetLastError());
-    unsigned long long big_items = 0;
-    CSBFS_HIP(hipMemcpyAsync(&big_items, scratch.p, sizeof(big_items), hipMemcpyDeviceToHost, st));
+    std::vector<unsigned long long> big_items(p);
+    CSBFS_HIP(hipMemcpyAsync(big_items.data(), scratch.p, sizeof(unsigned long long) * p,
+                             hipMemcpyDeviceToHost, st));
     CSBFS_HIP(hipStreamSynchronize(st));
 
     g->row_ptr = (int32_t *)rp.release();
@@ -310,10 +322,10 @@ extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t
     g->scratch = (unsigned long long *)scratch.release();
     g->nnz = total;
     g->max_block_nnz = maxb;
-    g->big_items = (int64_t)big_items;
+    g->big_items.assign(big_items.begin(), big_items.end());
     g->device_bytes = (int64_t)(sizeof(int32_t) * B * (R + 1) + sizeof(int64_t) * (B + 1) +
                                 sizeof(uint32_t) * total + sizeof(uint64_t) * B * W +
-                                sizeof(int32_t) * n + 256);
+                                sizeof(int32_t) * n + 8 * 64);
     *out = g.release();
     return CSBFS_OK;
 }

@@ -25,7 +25,7 @@ struct csbfs_graph {
     int64_t n_tuples = 0;
     int64_t nnz = 0;
     int64_t max_block_nnz = 0;
-    int64_t big_items = 0;  // queue items if every row were expanded at once
+    std::vector<int64_t> big_items;  // per block-row: queue items if every row were expanded at once
     int64_t device_bytes = 0;
     // block b = i * P + j: rows are sources u in R_j, columns targets in R_i
     int32_t *row_ptr = nullptr;       // [P*P][R + 1], offsets within the block
@@ -39,4 +39,7 @@ struct csbfs_graph {
 
 namespace csbfs {
 int graph_device_check(const csbfs_graph *g);
+// Sort every block row (descending target id); replaces *col by a new buffer.
+int sort_rows_desc(uint32_t **col, const int64_t *col_base, const int32_t *row_ptr, int64_t R,
+                   int32_t P, int64_t nnz, hipStream_t st);
 }

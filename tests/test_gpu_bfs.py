@@ -52,8 +52,9 @@ def test_directory_and_blocks(scale, p):
                 exp.setdefault(int(u), []).append(int(v))
             assert rp[0] == 0 and rp[-1] == len(col)
             for u in range(R):
-                got = sorted(col[rp[u]:rp[u + 1]].tolist())
-                assert got == sorted(exp.get(u, [])), (i, j, u)
+                row = col[rp[u]:rp[u + 1]].tolist()
+                assert row == sorted(row, reverse=True), (i, j, u)  # decreasing ids
+                assert sorted(row) == sorted(exp.get(u, [])), (i, j, u)
 
 
 def _check_search(eng, g, n, p, src, dst, root, adj, V, keep=True, max_levels=64):
@@ -95,18 +96,22 @@ def _check_search(eng, g, n, p, src, dst, root, adj, V, keep=True, max_levels=64
     return r
 
 
+MODES = {"auto": 0, "sparse": 8, "dense": 16}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("scale,p,nroots", [(10, 1, 16), (10, 2, 4), (10, 4, 4), (11, 8, 3),
-                                            (12, 4, 3), (13, 2, 2)])
-def test_search_matches_oracle(scale, p, nroots):
+                                            (12, 4, 3), (13, 2, 2), (14, 4, 2)])
+def test_search_matches_oracle(scale, p, nroots, mode):
     from paper_1208_5542_amd import csbfs
     n, src, dst = _graph(scale)
     g = csbfs.Graph(_dev(src), _dev(dst), n, p)
-    eng = csbfs.Engine(g, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS)
+    eng = csbfs.Engine(g, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS | MODES[mode])
     adj = oracle.Adjacency(n, src, dst)
     V = oracle.directory(n, p, src, dst).reshape(-1)
     roots = inputs.pick_roots(n, src, dst, nroots, inputs.graph_seed(scale) + 2)
     for root in roots:
-        log(f"search scale={scale} p={p} root={int(root)}")
+        log(f"search scale={scale} p={p} mode={mode} root={int(root)}")
         _check_search(eng, g, n, p, src, dst, int(root), adj, V)
 
 
@@ -122,12 +127,13 @@ def test_sparse_graph_many_levels():
     src = np.r_[src, extra[0]].astype(np.int64)
     dst = np.r_[dst, extra[1]].astype(np.int64)
     g = csbfs.Graph(_dev(src), _dev(dst), n, p)
-    eng = csbfs.Engine(g, max_levels=4096, flags=csbfs.FLAG_KEEP_STREAMS)
     adj = oracle.Adjacency(n, src, dst)
     V = oracle.directory(n, p, src, dst).reshape(-1)
-    log("search long path")
-    r = _check_search(eng, g, n, p, src, dst, int(perm[0]), adj, V, keep=False, max_levels=4096)
-    assert r.n_levels > 50
+    for mode, flag in MODES.items():
+        eng = csbfs.Engine(g, max_levels=4096, flags=flag)
+        log(f"search long path mode={mode}")
+        r = _check_search(eng, g, n, p, src, dst, int(perm[0]), adj, V, keep=False, max_levels=4096)
+        assert r.n_levels > 50
 
 
 def test_stats_truncated_beyond_max_levels():
@@ -155,12 +161,13 @@ def test_high_degree_rows_use_chunk_queue():
     src = np.r_[np.full(len(leaves), hub), rng.integers(0, n, 3000)].astype(np.int64)
     dst = np.r_[leaves, rng.integers(0, n, 3000)].astype(np.int64)
     g = csbfs.Graph(_dev(src), _dev(dst), n, p)
-    eng = csbfs.Engine(g, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS)
     adj = oracle.Adjacency(n, src, dst)
     V = oracle.directory(n, p, src, dst).reshape(-1)
-    for root in (hub, int(leaves[0])):
-        log(f"star root={root}")
-        _check_search(eng, g, n, p, src, dst, root, adj, V)
+    for mode, flag in MODES.items():
+        eng = csbfs.Engine(g, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS | flag)
+        for root in (hub, int(leaves[0])):
+            log(f"star mode={mode} root={root}")
+            _check_search(eng, g, n, p, src, dst, root, adj, V)
 
 
 def test_isolated_root_and_empty_graph():
