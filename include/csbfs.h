@@ -93,7 +93,9 @@ typedef struct csbfs_graph csbfs_graph;
  * V_{i,j} (Eq. dir-vec) is the non-empty-row bitmap of block (i, j). The
  * input buffers are only read and may be freed after the call. Blocking.
  * Errors: EINVAL (null pointers, n_tuples < 0), ERANGE (n or p not
- * admissible, a tuple id outside [0, n)), EOVERFLOW, EHIP.
+ * admissible, a tuple id outside [0, n)), EOVERFLOW, ECORRUPT (the built
+ * CSR failed its consistency check: a column id outside its block or an
+ * adjacency total other than 2 * n_tuples), EHIP.
  */
 int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t n_tuples, int64_t n,
                       int32_t p, void *stream, csbfs_graph **out);

@@ -176,6 +176,28 @@ __global__ void k_degree(const int32_t *row_ptr, int64_t R, int32_t P, int64_t n
     }
 }
 
+// Consistency of a built graph: the largest column id (must be below R) and
+// the degree total (must equal nnz).
+__global__ void k_check(const uint32_t *col, int64_t nnz, const int32_t *deg, int64_t n,
+                        unsigned long long *out) {
+    uint32_t mx = 0;
+    unsigned long long ds = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz; k += stride)
+        mx = col[k] > mx ? col[k] : mx;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += stride)
+        ds += (unsigned long long)deg[u];
+    for (int d = 32; d > 0; d >>= 1) {
+        const uint32_t o = __shfl_xor(mx, d, 64);
+        mx = o > mx ? o : mx;
+        ds += __shfl_xor(ds, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&out[0], (unsigned long long)mx);
+        if (ds) atomicAdd(&out[1], ds);
+    }
+}
+
 __global__ void k_count_m(const int32_t *level, const int32_t *deg, int64_t n,
                           unsigned long long *out) {
     unsigned long long s = 0;
@@ -296,7 +318,7 @@ extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t
     }
     {
         uint32_t *c = (uint32_t *)col.p;
-        int src_rc = sort_rows_desc(&c, (const int64_t *)cb.p, (const int32_t *)rp.p, R, p, total, st);
+        int src_rc = sort_rows_desc(&c, base.data(), (const int32_t *)rp.p, R, p, total, st);
         col.p = c;
         if (src_rc) return src_rc;
     }
@@ -312,6 +334,17 @@ extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t
     CSBFS_HIP(hipMemcpyAsync(big_items.data(), scratch.p, sizeof(unsigned long long) * p,
                              hipMemcpyDeviceToHost, st));
     CSBFS_HIP(hipStreamSynchronize(st));
+    // never hand the search a column id outside its block or a lost entry
+    CSBFS_HIP(hipMemsetAsync(scratch.p, 0, 2 * sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_check, dim3(4096), dim3(kThreads), 0, st, (const uint32_t *)col.p, total,
+                       (const int32_t *)deg.p, n, (unsigned long long *)scratch.p);
+    CSBFS_HIP(hipGetLastError());
+    unsigned long long chk[2] = {0, 0};
+    CSBFS_HIP(hipMemcpyAsync(chk, scratch.p, sizeof(chk), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    if (total > 0 && (chk[0] >= (unsigned long long)R || chk[1] != (unsigned long long)total))
+        return fail(CSBFS_ECORRUPT, "csbfs_graph_build: internal consistency check of the block "
+                                    "CSR failed (column id or degree total)");
 
     g->row_ptr = (int32_t *)rp.release();
     g->col_base = (int64_t *)cb.release();

@@ -40,6 +40,6 @@ struct csbfs_graph {
 namespace csbfs {
 int graph_device_check(const csbfs_graph *g);
 // Sort every block row (descending target id); replaces *col by a new buffer.
-int sort_rows_desc(uint32_t **col, const int64_t *col_base, const int32_t *row_ptr, int64_t R,
+int sort_rows_desc(uint32_t **col, const int64_t *col_base_host, const int32_t *row_ptr, int64_t R,
                    int32_t P, int64_t nnz, hipStream_t st);
 }

@@ -2,6 +2,7 @@
 // with rocPRIM's segmented radix sort. Setup only; the search never calls it.
 // Descending rows let the parent search of a new vertex stop at its first
 // frontier neighbour, which is then the highest-labelled one.
+#include <algorithm>
 #include <cstring>
 
 #include <rocprim/rocprim.hpp>
@@ -11,48 +12,56 @@
 namespace csbfs {
 namespace {
 
-// Global col offset of row s = b * R + u (s = P*P*R gives the total).
+// Offset of row s of one block within that block's col (s = R gives its size).
 struct RowOffset {
-    const int64_t *col_base;
-    const int32_t *row_ptr;
-    int64_t R;
-    int64_t nrows;
-    __host__ __device__ uint32_t operator()(uint32_t s) const {
-        if ((int64_t)s >= nrows) return (uint32_t)col_base[nrows / R];
-        const int64_t b = s / R, u = s - b * R;
-        return (uint32_t)(col_base[b] + row_ptr[b * (R + 1) + u]);
-    }
+    const int32_t *row_ptr;  // the block's R + 1 row offsets
+    __host__ __device__ uint32_t operator()(uint32_t s) const { return (uint32_t)row_ptr[s]; }
 };
 
 }  // namespace
 
-int sort_rows_desc(uint32_t **col, const int64_t *col_base, const int32_t *row_ptr, int64_t R,
+int sort_rows_desc(uint32_t **col, const int64_t *col_base_host, const int32_t *row_ptr, int64_t R,
                    int32_t P, int64_t nnz, hipStream_t st) {
-    const int64_t nrows = (int64_t)P * P * R;
     if (nnz == 0) return CSBFS_OK;
-    if (nnz >= ((int64_t)1 << 32) - 1 || nrows >= ((int64_t)1 << 32) - 1)
-        return fail(CSBFS_EOVERFLOW, "graph too large for the row sort");
-    RowOffset fo{col_base, row_ptr, R, nrows};
+    if (R >= ((int64_t)1 << 31) - 1) return fail(CSBFS_EOVERFLOW, "block too large for the row sort");
     rocprim::counting_iterator<uint32_t> cnt(0);
-    auto begin = rocprim::make_transform_iterator(cnt, fo);
-    auto end = rocprim::make_transform_iterator(cnt + 1, fo);
-    uint32_t *tmp = nullptr;
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
     int bits = 1;
     while (((int64_t)1 << bits) < R) ++bits;
-    CSBFS_HIP(rocprim::segmented_radix_sort_keys_desc(nullptr, ws_bytes, *col, tmp, (unsigned)nnz,
-                                                      (unsigned)nrows, begin, end, 0, bits, st));
+    // one sort per block: every block has fewer than 2^31 entries
+    int64_t max_block = 0;
+    for (int64_t b = 0; b < (int64_t)P * P; ++b)
+        max_block = std::max(max_block, col_base_host[b + 1] - col_base_host[b]);
+    size_t ws_bytes = 0;
+    {
+        RowOffset fo{row_ptr};
+        auto begin = rocprim::make_transform_iterator(cnt, fo);
+        auto end = rocprim::make_transform_iterator(cnt + 1, fo);
+        CSBFS_HIP(rocprim::segmented_radix_sort_keys_desc(nullptr, ws_bytes, *col, *col,
+                                                          (unsigned)max_block, (unsigned)R, begin,
+                                                          end, 0, bits, st));
+    }
+    uint32_t *tmp = nullptr;
+    void *ws = nullptr;
     CSBFS_HIP(hipMalloc(&tmp, sizeof(uint32_t) * nnz));
     hipError_t e = hipMalloc(&ws, ws_bytes > 0 ? ws_bytes : 1);
-    if (e != hipSuccess) {
-        (void)hipFree(tmp);
-        return hip_fail(e, "hipMalloc(sort workspace)", __FILE__, __LINE__);
+    for (int64_t b = 0; e == hipSuccess && b < (int64_t)P * P; ++b) {
+        const int64_t base = col_base_host[b], size = col_base_host[b + 1] - base;
+        if (size == 0) continue;
+        RowOffset fo{row_ptr + b * (R + 1)};
+        auto begin = rocprim::make_transform_iterator(cnt, fo);
+        auto end = rocprim::make_transform_iterator(cnt + 1, fo);
+        size_t need = 0;
+        e = rocprim::segmented_radix_sort_keys_desc(nullptr, need, *col + base, tmp + base,
+                                                    (unsigned)size, (unsigned)R, begin, end, 0,
+                                                    bits, st);
+        if (e == hipSuccess && need > ws_bytes) e = hipErrorInvalidValue;
+        if (e == hipSuccess)
+            e = rocprim::segmented_radix_sort_keys_desc(ws, need, *col + base, tmp + base,
+                                                        (unsigned)size, (unsigned)R, begin, end, 0,
+                                                        bits, st);
     }
-    e = rocprim::segmented_radix_sort_keys_desc(ws, ws_bytes, *col, tmp, (unsigned)nnz,
-                                                (unsigned)nrows, begin, end, 0, bits, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(ws);
+    if (ws) (void)hipFree(ws);
     if (e != hipSuccess) {
         (void)hipFree(tmp);
         return hip_fail(e, "segmented_radix_sort_keys_desc", __FILE__, __LINE__);
