@@ -601,7 +601,8 @@ struct csbfs_engine {
     size_t counters_bytes = 0;
     LevelCounters lc{};
     int32_t *status = nullptr;
-    unsigned long long *host_ctl = nullptr;  // pinned [2]
+    unsigned long long *host_ctl = nullptr;  // pinned [2][2]: frontier counts, double-buffered
+    hipEvent_t count_ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> events;
     int32_t last_levels = 0;
     // The dense evaluation is used only when asked for: measured on R-MAT
@@ -623,6 +624,8 @@ void engine_release(csbfs_engine *e) {
     for (void *p : e->allocs) (void)hipFree(p);
     e->allocs.clear();
     if (e->host_ctl) (void)hipHostFree(e->host_ctl);
+    for (hipEvent_t ev : e->count_ev)
+        if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : e->events)
         if (ev) (void)hipEventDestroy(ev);
     e->events.clear();
@@ -705,11 +708,19 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
         engine_release(e);
         return hip_fail(herr, "hipMemcpy(qoff)", __FILE__, __LINE__);
     }
-    herr = hipHostMalloc((void **)&e->host_ctl, 2 * sizeof(unsigned long long));
+    herr = hipHostMalloc((void **)&e->host_ctl, 4 * sizeof(unsigned long long));
     if (herr != hipSuccess) {
         e->host_ctl = nullptr;
         engine_release(e);
         return hip_fail(herr, "hipHostMalloc", __FILE__, __LINE__);
+    }
+    for (auto &ev : e->count_ev) {
+        herr = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (herr != hipSuccess) {
+            ev = nullptr;
+            engine_release(e);
+            return hip_fail(herr, "hipEventCreate", __FILE__, __LINE__);
+        }
     }
     if (flags & CSBFS_FLAG_TIMING) {
         e->events.assign((size_t)max_levels * kEvPerLevel, nullptr);
@@ -813,24 +824,42 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     wb.dst_base = e->view;
     wb.status = e->status;
 
-    unsigned long long cur_count = 1;  // |f^k|, read back after each update
-    int64_t k = 0;
-    for (;; ++k) {
-        const int64_t sk = slot_of(e, k), sn = slot_of(e, k + 1);
-        if (k + 1 >= e->L) {
-            rc = reset_overflow_slot(e, st);
-            if (rc) return rc;
+    bool dense = e->dense_default;
+    if (e->flags & CSBFS_FLAG_SPARSE_ONLY) dense = false;
+    if (e->flags & CSBFS_FLAG_DENSE_ONLY) dense = true;
+
+    // Iteration j: the messages carrying f^j (j >= 1: sieve + compress, then
+    // decode into the views), the expansion of f^j, the update producing
+    // f^{j+1} and the copy of |f^{j+1}| to host slot (j + 1) & 1.
+    auto enqueue_iter = [&](int64_t j, unsigned long long known) -> int {
+        const int64_t sj = slot_of(e, j), sn = slot_of(e, j + 1);
+        if (j + 1 >= e->L) {
+            const int r2 = reset_overflow_slot(e, st);
+            if (r2) return r2;
         }
-        bool dense = e->dense_default;
-        if (e->flags & CSBFS_FLAG_SPARSE_ONLY) dense = false;
-        if (e->flags & CSBFS_FLAG_DENSE_ONLY) dense = true;
-        hipEvent_t *ev = (timing && k < e->L) ? &e->events[(size_t)k * kEvPerLevel] : nullptr;
+        hipEvent_t *evp = (timing && j >= 1 && j - 1 < e->L) ? &e->events[(size_t)(j - 1) * kEvPerLevel] : nullptr;
+        hipEvent_t *ev = (timing && j < e->L) ? &e->events[(size_t)j * kEvPerLevel] : nullptr;
+        if (j >= 1) {
+            // a4 + a5: sieve and compress every stream i -> j
+            const int64_t arena_slot = keep ? sj : 0;
+            wb.out_base = e->arena + arena_slot * S * e->cap;
+            wb.n_words = e->lc.words + sj * S;
+            wb.stat_sieved_bits = e->lc.sbits + sj * S;
+            wb.stat_unsieved_words = e->lc.uwords + sj * P;
+            int r2 = launch_wah_encode(wb, st);
+            if (r2) return r2;
+            if (evp) CSBFS_HIP(hipEventRecord(evp[3], st));
+            // a6: the stream slots are the receive buffers; a7: decode into the views
+            r2 = launch_wah_decode(wb, st);
+            if (r2) return r2;
+            if (evp) CSBFS_HIP(hipEventRecord(evp[4], st));
+        }
         if (ev) CSBFS_HIP(hipEventRecord(ev[0], st));
-        // a1: expand f^k; small tiles when the frontier is large, so that
-        // every wave gets work, large ones when it is small
-        const bool wide = (double)cur_count * 64.0 >= (double)n;
+        // a1: expand f^j; small tiles when the last known frontier is large,
+        // so that every wave gets work, large ones when it is small
+        const bool wide = (double)known * 64.0 >= (double)n;
         ea.tile_words = wide ? 16 : 64;
-        ea.edges = e->lc.edges + sk;
+        ea.edges = e->lc.edges + sj;
         if (dense) {
             hipLaunchKernelGGL(expand_kernel<true>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
             CSBFS_HIP(hipGetLastError());
@@ -845,30 +874,35 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
             CSBFS_HIP(hipGetLastError());
         }
         if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
-        // a2: mask, visit, f^{k+1}; a3: reduction of |f^{k+1}|
-        UpdateArgs ua{parent, e->seen, e->pi, e->f, e->view, level, (int32_t)(k + 1), words, W, (int32_t)P, e->lc.rank + sn * P,
-                      e->lc.ctl + 2 * sn, e->ctrs};
+        // a2: mask, visit, f^{j+1}; a3: reduction of |f^{j+1}|
+        UpdateArgs ua{parent, e->seen, e->pi, e->f, e->view, level, (int32_t)(j + 1), words, W,
+                      (int32_t)P, e->lc.rank + sn * P, e->lc.ctl + 2 * sn, e->ctrs};
         hipLaunchKernelGGL(update_kernel, dim3(upd_grid), dim3(kUpdThreads), 0, st, ua);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
-        CSBFS_HIP(hipMemcpyAsync(e->host_ctl, e->lc.ctl + 2 * sn, 2 * sizeof(unsigned long long),
+        const int hs = (int)((j + 1) & 1);
+        CSBFS_HIP(hipMemcpyAsync(e->host_ctl + 2 * hs, e->lc.ctl + 2 * sn, 2 * sizeof(unsigned long long),
                                  hipMemcpyDeviceToHost, st));
-        CSBFS_HIP(hipStreamSynchronize(st));
-        if (e->host_ctl[0] == 0) break;
-        cur_count = e->host_ctl[0];
-        // a4 + a5: sieve and compress every stream i -> j
-        const int64_t arena_slot = keep ? sn : 0;
-        wb.out_base = e->arena + arena_slot * S * e->cap;
-        wb.n_words = e->lc.words + sn * S;
-        wb.stat_sieved_bits = e->lc.sbits + sn * S;
-        wb.stat_unsieved_words = e->lc.uwords + sn * P;
-        rc = launch_wah_encode(wb, st);
+        CSBFS_HIP(hipEventRecord(e->count_ev[hs], st));
+        return CSBFS_OK;
+    };
+
+    // The host reads |f^{k+1}| while iteration k + 1 already runs on the GPU
+    // (one level of look-ahead). When f^{k+1} turns out empty, that iteration
+    // ran on empty views and an empty frontier: it changed no output, and its
+    // counters lie past the last reported level.
+    unsigned long long known = 1;  // |f^0|
+    rc = enqueue_iter(0, known);
+    if (rc) return rc;
+    int64_t k = 0;
+    for (;; ++k) {
+        rc = enqueue_iter(k + 1, known);
         if (rc) return rc;
-        if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
-        // a6: the stream slots are the receive buffers; a7: decode into the views
-        rc = launch_wah_decode(wb, st);
-        if (rc) return rc;
-        if (ev) CSBFS_HIP(hipEventRecord(ev[4], st));
+        const int hs = (int)((k + 1) & 1);
+        CSBFS_HIP(hipEventSynchronize(e->count_ev[hs]));
+        const unsigned long long cnt = e->host_ctl[2 * hs];
+        if (cnt == 0) break;
+        known = cnt;
     }
     const int64_t nl = k + 1;  // levels 0..k
     *n_levels = (int32_t)(nl < INT32_MAX ? nl : INT32_MAX);
