@@ -46,7 +46,23 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None, help="also write a detailed report here")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy(mib: int):
+    """A plain copy kernel of known size: reads and writes mib MiB once each,
+    so hardware byte counters taken on it give their scale factor."""
+    import torch
+    n = mib << 20
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
 
 
 def expand_kernel_hash() -> str:
@@ -109,6 +125,9 @@ def cpu_baseline(n, src, dst, p, roots, budget_s):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
               "of the level loop is a design note, not a measured path", flush=True)
