@@ -1,0 +1,86 @@
+"""The C ABI library loads, exports every entry point include/csbfs.h
+declares, and rejects bad arguments on the host before touching a GPU
+(CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+REPO = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(REPO, "include", "csbfs.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(csbfs_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1208_5542_amd import csbfs
+    if not os.path.exists(csbfs.LIB_PATH):
+        from paper_1208_5542_amd import _build
+        _build.build_csbfs()
+    return csbfs.lib()
+
+
+def test_header_declares_the_expected_entry_points():
+    names = _declared()
+    for must in ("csbfs_graph_build", "csbfs_bfs", "csbfs_wah_encode", "csbfs_wah_decode_or",
+                 "csbfs_engine_create", "csbfs_count_traversed_tuples"):
+        assert must in names
+    assert len(names) >= 18
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings(lib):
+    from paper_1208_5542_amd import csbfs
+    assert csbfs.version() == 10000
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert csbfs.strerror(code) != "unknown status"
+    assert csbfs.strerror(-99) == "unknown status"
+
+
+def test_host_side_argument_checks(lib):
+    vp = ctypes.c_void_p
+    h = vp()
+    # graph build: null tuples, bad sizes, p not dividing n, n/p not a multiple of 64
+    assert lib.csbfs_graph_build(None, None, 5, 1024, 4, None, ctypes.byref(h)) == -1
+    assert lib.csbfs_graph_build(None, None, 0, 1000, 4, None, ctypes.byref(h)) == -2
+    assert lib.csbfs_graph_build(None, None, 0, 1024, 3, None, ctypes.byref(h)) == -2
+    assert b"p | n" in lib.csbfs_last_error()
+    assert lib.csbfs_graph_build(None, None, 0, 2048, 64, None, ctypes.byref(h)) == -2
+    assert lib.csbfs_graph_build(None, None, 0, 32, 1, None, ctypes.byref(h)) == -2
+    assert lib.csbfs_graph_build(None, None, 0, 1 << 31, 1, None, ctypes.byref(h)) == -2
+    assert lib.csbfs_graph_build(None, None, -1, 1024, 1, None, ctypes.byref(h)) == -1
+    assert lib.csbfs_graph_build(None, None, 0, 1024, 1, None, None) == -1
+    # engine and search on null handles
+    assert lib.csbfs_engine_create(None, 64, 0, ctypes.byref(h)) == -1
+    assert lib.csbfs_bfs(None, 0, None, None, None, 0, None, None) == -1
+    assert lib.csbfs_engine_stream_words(None, None, 0) == -1
+    assert lib.csbfs_engine_copy_stream(None, 0, 0, 0, None, 0, None, None) == -1
+    assert lib.csbfs_graph_get_info(None, None) == -1
+    assert lib.csbfs_graph_free(None) == 0
+    assert lib.csbfs_engine_free(None) == 0
+    assert lib.csbfs_count_traversed_tuples(None, None, None, None) == -1
+    # codec sizing and argument checks
+    assert lib.csbfs_wah_capacity(0) == 1
+    assert lib.csbfs_wah_capacity(63) == 2
+    assert lib.csbfs_wah_capacity(1 << 20) == (1 << 20) // 63 + 1
+    assert lib.csbfs_wah_capacity(-1) == -1
+    assert lib.csbfs_wah_workspace_bytes(1 << 20) > 0
+    assert lib.csbfs_wah_encode(None, None, 64, None, 0, None, None, 0, None) == -1
+    assert lib.csbfs_wah_decode_or(None, 1, 64, None, None, None, 0, None) == -1
+
+
+def test_package_import_does_not_need_a_gpu():
+    import importlib
+    import paper_1208_5542_amd.csbfs as m
+    importlib.reload(m)
+    assert m.FLAG_TIMING == 1 and m.FLAG_DENSE_ONLY == 16
