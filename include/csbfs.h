@@ -234,6 +234,59 @@ int csbfs_engine_copy_stream(const csbfs_engine *e, int32_t k, int32_t i, int32_
                              void *stream);
 
 /* ======================================================================== */
+/* Batched searches: up to 64 roots at once (multi-source BFS).             */
+/* ======================================================================== */
+
+/*
+ * A batched search runs Algorithm 3 for up to 64 roots together. Every
+ * vertex carries a 64-bit visit mask (bit r: reached by root r's search);
+ * the expansion pushes a source's mask of frontier roots along each edge
+ * once. Each root keeps its own frontier bitmap (one bit-plane per root),
+ * so every root's messages are exactly those of its single-root search:
+ * p x p streams per root and level, sieved by the same directory and
+ * WAH-64 compressed, all in one launch per step. Levels only (no parents).
+ */
+typedef struct csbfs_batch_engine csbfs_batch_engine;
+
+/* Workspace for batches of up to max_roots (1..64) roots and max_levels
+ * levels of counters (1..65536). Flags: CSBFS_FLAG_TIMING,
+ * CSBFS_FLAG_KEEP_STREAMS, CSBFS_FLAG_NO_SIEVE. The graph must outlive the
+ * engine. Blocking. Errors: EINVAL, EHIP. */
+int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots, int32_t max_levels,
+                              uint32_t flags, csbfs_batch_engine **out);
+
+/* Release a batch engine. NULL is accepted. Blocking. */
+int csbfs_batch_engine_free(csbfs_batch_engine *e);
+
+/*
+ * One batched search.
+ *   roots   host int64[n_roots], 1 <= n_roots <= max_roots, each in [0, n)
+ *           (repeats allowed).
+ *   level   device int32[n_roots * n]: level[r * n + v] = hop distance of v
+ *           from roots[r], -1 if unreachable.
+ *   stats   host csbfs_level_stats[stats_cap] or NULL: per level, summed
+ *           over the roots whose frontier at that level is not empty
+ *           (frontier, bits and bytes as for csbfs_bfs; edges counts the
+ *           adjacency entries the batch scanned once for all its roots).
+ *   n_levels host: max over roots of (max level + 1).
+ * Blocking. Errors: EINVAL, ERANGE (a root outside [0, n)), ECORRUPT, EHIP.
+ */
+int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int32_t n_roots, int32_t *level,
+                    csbfs_level_stats *stats, int32_t stats_cap, int32_t *n_levels, void *stream);
+
+/* Word counts of the last batch's streams: words host int32[cap_levels *
+ * n_roots * p * p], words[((k * n_roots + r) * p + i) * p + j] = words of
+ * root r's stream from P_i to P_j carrying level k (0 when root r's level-k
+ * frontier is empty, and for k = 0). Blocking. Errors: EINVAL. */
+int csbfs_batch_stream_words(const csbfs_batch_engine *e, int32_t *words, int32_t cap_levels);
+
+/* Copy root r's stream from P_i to P_j carrying level k of the last batch
+ * (needs CSBFS_FLAG_KEEP_STREAMS). As csbfs_engine_copy_stream. */
+int csbfs_batch_copy_stream(const csbfs_batch_engine *e, int32_t k, int32_t r, int32_t i,
+                            int32_t j, uint64_t *dst, int64_t cap_words, int64_t *n_words_out,
+                            void *stream);
+
+/* ======================================================================== */
 /* WAH-64 codec on device buffers (Sec. IV).                                */
 /* ======================================================================== */
 

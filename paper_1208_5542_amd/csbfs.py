@@ -75,6 +75,13 @@ def lib():
         "csbfs_engine_stream_words": ([vp, vp, i32], ctypes.c_int),
         "csbfs_engine_copy_stream": ([vp, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp],
                                      ctypes.c_int),
+        "csbfs_batch_engine_create": ([vp, i32, i32, u32, ctypes.POINTER(vp)], ctypes.c_int),
+        "csbfs_batch_engine_free": ([vp], ctypes.c_int),
+        "csbfs_batch_bfs": ([vp, vp, i32, vp, ctypes.POINTER(LevelStats), i32, ctypes.POINTER(i32), vp],
+                            ctypes.c_int),
+        "csbfs_batch_stream_words": ([vp, vp, i32], ctypes.c_int),
+        "csbfs_batch_copy_stream": ([vp, i32, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp],
+                                    ctypes.c_int),
         "csbfs_wah_capacity": ([i64], i64),
         "csbfs_wah_workspace_bytes": ([i64], sz),
         "csbfs_wah_encode": ([vp, vp, i64, vp, i64, vp, vp, sz, vp], ctypes.c_int),
@@ -234,6 +241,72 @@ class Engine:
         nw = ctypes.c_int64()
         _check(lib().csbfs_engine_copy_stream(self._h, k, i, j, _ptr(out), cap, ctypes.byref(nw),
                                               _stream(stream)), "csbfs_engine_copy_stream")
+        return out[: int(nw.value)]
+
+
+@dataclass
+class BatchResult:
+    level: torch.Tensor  # (n_roots, n) int32
+    n_levels: int
+    stats: list[dict]
+
+
+class BatchEngine:
+    """Workspace for batched searches of up to 64 roots (csbfs_batch_engine_create)."""
+
+    def __init__(self, graph: Graph, max_roots: int = 64, max_levels: int = 64, flags: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().csbfs_batch_engine_create(graph.handle, max_roots, max_levels, flags, ctypes.byref(h)),
+               "csbfs_batch_engine_create")
+        self._h = h
+        self.graph = graph
+        self.max_roots = max_roots
+        self.max_levels = max_levels
+        self.flags = flags
+        self.n_roots = 0
+        self._stats = (LevelStats * max_levels)()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().csbfs_batch_engine_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bfs(self, roots, level: torch.Tensor | None = None, stream=None,
+            with_stats: bool = True) -> BatchResult:
+        roots = (ctypes.c_int64 * len(roots))(*[int(r) for r in roots])
+        B, n = len(roots), self.graph.n
+        if level is None:
+            level = torch.empty((B, n), dtype=torch.int32, device="cuda")
+        nl = ctypes.c_int32()
+        cap = self.max_levels if with_stats else 0
+        _check(lib().csbfs_batch_bfs(self._h, roots, B, _ptr(level), self._stats if with_stats else None,
+                                     cap, ctypes.byref(nl), _stream(stream)), "csbfs_batch_bfs")
+        self.n_roots = B
+        n_levels = int(nl.value)
+        stats = [self._stats[k].as_dict() for k in range(min(n_levels, cap))]
+        return BatchResult(level.view(B, n), n_levels, stats)
+
+    def stream_words(self, n_levels: int):
+        """int32 (n_levels, n_roots, p, p) word counts of the last batch's streams."""
+        import numpy as np
+        p, B = self.graph.p, self.n_roots
+        out = np.zeros(n_levels * B * p * p, dtype=np.int32)
+        _check(lib().csbfs_batch_stream_words(self._h, out.ctypes.data_as(ctypes.c_void_p), n_levels),
+               "csbfs_batch_stream_words")
+        return out.reshape(n_levels, B, p, p)
+
+    def stream(self, k: int, r: int, i: int, j: int, stream=None) -> torch.Tensor:
+        cap = wah_capacity(self.graph.range)
+        out = torch.zeros(cap, dtype=torch.int64, device="cuda")
+        nw = ctypes.c_int64()
+        _check(lib().csbfs_batch_copy_stream(self._h, k, r, i, j, _ptr(out), cap, ctypes.byref(nw),
+                                             _stream(stream)), "csbfs_batch_copy_stream")
         return out[: int(nw.value)]
 
 

@@ -1,0 +1,741 @@
+// Batched searches: Algorithm 3 (Sec. V.B) for up to 64 roots at once.
+//
+// Vertex v carries a visit mask vis[v] (bit r: reached by root r) and, during
+// a level, a mask nx[v] of the roots that discovered it. Each root keeps its
+// own frontier bitmap: plane r of `f` holds f_r, and plane r of the views
+// holds the pieces P_i received for root r. One level:
+//
+//   expand   every view word position (i, j, q) is read in all planes at
+//            once (lane = root) and transposed with ballots into the masks of
+//            its 64 sources (lane = source); a source's mask travels along
+//            its row of block (i, j) once, for all its roots: nx[v] |= m &
+//            ~vis[v]. Long rows go to per-processor chunk queues.
+//   update   new = nx & ~vis; vis |= new; level[r][v] = k + 1 for each new
+//            bit r; the new masks are transposed back into the planes of
+//            f^{k+1}, and per-root frontier sizes are reduced.
+//   messages plane r of f^{k+1} is sieved, WAH-64 compressed, exchanged and
+//            decoded exactly as in the single-root search (wah.hip, one
+//            launch for all planes), so every root's streams equal those of
+//            its own search.
+//
+// Levels only: the (select, max) parents would need one 32-bit slot per
+// (vertex, root) and a max-reduction per root and edge.
+#include <vector>
+
+#include "device.hpp"
+#include "graph.hpp"
+
+namespace csbfs {
+namespace {
+
+constexpr int kBThreads = 256;
+constexpr int kBUnroll = 4;
+constexpr int kBEvPerLevel = 5;
+constexpr int kMaxRoots = 64;
+
+struct BItem {
+    uint64_t mask;  // roots whose frontier holds the source
+    int32_t block;
+    int32_t u_local;
+    int32_t start;  // offsets within the block's col
+    int32_t end;
+};
+
+struct BArgs {
+    uint64_t *view;  // [B][P * P * W] planes of views
+    int64_t vplane;  // words per view plane
+    int32_t B;
+    const int32_t *row_ptr;
+    const int64_t *col_base;
+    const uint32_t *col;
+    const uint64_t *vis;  // [n]
+    uint64_t *nx;         // [n]
+    BItem *queue;
+    const int64_t *qoff;     // [P + 1]
+    uint32_t *queue_count;   // [P]
+    int64_t R;
+    int64_t W;
+    int32_t P;
+    unsigned long long *edges;
+    int32_t *status;
+};
+
+// Push kBUnroll (target v, root mask m) pairs; loads first, then atomics.
+__device__ __forceinline__ void brelax(const BArgs &a, const int64_t (&v)[kBUnroll],
+                                       const uint64_t (&m)[kBUnroll], const bool (&ok)[kBUnroll]) {
+    uint64_t add[kBUnroll];
+#pragma unroll
+    for (int k = 0; k < kBUnroll; ++k) add[k] = ok[k] ? (m[k] & ~a.vis[v[k]]) : 0ull;
+    uint64_t have[kBUnroll];
+#pragma unroll
+    for (int k = 0; k < kBUnroll; ++k)
+        have[k] = add[k] ? __hip_atomic_load(&a.nx[v[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ~0ull;
+#pragma unroll
+    for (int k = 0; k < kBUnroll; ++k)
+        if (add[k] & ~have[k]) atomicOr((unsigned long long *)&a.nx[v[k]], (unsigned long long)add[k]);
+}
+
+// Orders a wave's LDS stores before its later LDS loads by other lanes (and
+// the loads before the next stores): LDS operations of one wave complete in
+// order, so only the compiler must be kept from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wave's tile: kBTile consecutive words of every root plane. Loads and
+// stores of a tile move 4 roots x kBTile words (four 128-byte lines) per
+// instruction; LDS turns them around so that lane r holds root r's word.
+constexpr int kBTile = 16;
+constexpr int kBRootsPerOp = 64 / kBTile;
+
+__global__ __launch_bounds__(kBThreads) void bexpand_kernel(BArgs a) {
+    __shared__ uint64_t tile[kBThreads / 64][kBTile][kMaxRoots];
+    const int lane = threadIdx.x & 63;
+    uint64_t(*tw)[kMaxRoots] = tile[threadIdx.x >> 6];
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t npos = (int64_t)a.P * a.P * a.W;
+    const int64_t ntiles = (npos + kBTile - 1) / kBTile;
+    const int t_ld = lane % kBTile, r_ld = lane / kBTile;
+    const int nsteps = (a.B + kBRootsPerOp - 1) / kBRootsPerOp;
+    unsigned long long edges = 0;
+    for (int64_t tl = wave; tl < ntiles; tl += nwaves) {
+        const int64_t pos0 = tl * kBTile;
+        uint64_t anyw = 0;
+        for (int s = 0; s < nsteps; ++s) {
+            const int r = r_ld + kBRootsPerOp * s;
+            const int64_t p = pos0 + t_ld;
+            uint64_t w = 0;
+            if (r < a.B && p < npos) {
+                uint64_t *src = a.view + r * a.vplane + p;
+                w = *src;
+                if (w) *src = 0;  // the views are empty again when the level ends
+            }
+            tw[t_ld][r] = w;
+            anyw |= w;
+        }
+        wave_lds_sync();
+        if (__ballot(anyw != 0)) {
+            for (int t = 0; t < kBTile; ++t) {
+                // lane r: root r's view word at this position
+                const uint64_t w = lane < a.B ? tw[t][lane] : 0ull;
+                if (!__ballot(w != 0)) continue;
+                const int64_t pos = pos0 + t;
+                // transpose: lane b gets the roots in whose frontier source b is
+                const uint64_t any = wave_or64(w);
+                uint64_t mymask = 0;
+                for (uint64_t it = any; it; it &= it - 1) {
+                    const int b = __ffsll((unsigned long long)it) - 1;
+                    const uint64_t m = __ballot((w >> b) & 1);
+                    if (lane == b) mymask = m;
+                }
+                const int64_t blk = pos / a.W;
+                const int64_t q = pos - blk * a.W;
+                const int32_t i = (int32_t)(blk / a.P);
+                const int64_t ul = (q << 6) + lane;
+                int32_t rs = 0, deg = 0;
+                if (mymask) {
+                    const int32_t *rp = a.row_ptr + blk * (a.R + 1) + ul;
+                    rs = rp[0];
+                    deg = rp[1] - rs;
+                }
+                const int32_t items = deg > kBigRow ? (deg + kBigChunk - 1) / kBigChunk : 0;
+                const int32_t items_incl = wave_incl_scan_i32(items);
+                const int32_t items_total = __shfl(items_incl, 63, 64);
+                if (items_total) {
+                    uint32_t qbase = 0;
+                    if (lane == 63) qbase = atomicAdd(&a.queue_count[i], (uint32_t)items_total);
+                    qbase = __shfl(qbase, 63, 64);
+                    if (items) {
+                        const int64_t qpos = (int64_t)qbase + items_incl - items;
+                        const int64_t qcap = a.qoff[i + 1] - a.qoff[i];
+                        if (qpos + items > qcap) {
+                            *a.status = 2;  // a row is queued at most once per level: unreachable
+                        } else {
+                            for (int32_t c = 0; c < items; ++c) {
+                                BItem it;
+                                it.mask = mymask;
+                                it.block = (int32_t)blk;
+                                it.u_local = (int32_t)ul;
+                                it.start = rs + c * kBigChunk;
+                                it.end = min(rs + deg, rs + (c + 1) * kBigChunk);
+                                a.queue[a.qoff[i] + qpos + c] = it;
+                            }
+                        }
+                        deg = 0;
+                    }
+                }
+                const int32_t incl = wave_incl_scan_i32(deg);
+                const int32_t total = __shfl(incl, 63, 64);
+                const int32_t excl = incl - deg;
+                edges += (unsigned long long)total;
+                const uint32_t *colb = a.col + a.col_base[blk];
+                const int64_t vbase = (int64_t)i * a.R;
+                for (int32_t e0 = 0; e0 < total; e0 += 64 * kBUnroll) {
+                    int64_t v[kBUnroll];
+                    uint64_t m[kBUnroll];
+                    bool ok[kBUnroll];
+#pragma unroll
+                    for (int k = 0; k < kBUnroll; ++k) {
+                        const int32_t e = e0 + 64 * k + lane;
+                        ok[k] = e < total;
+                        const int o = owner_lane(excl, ok[k] ? e : total - 1);
+                        const int32_t ex = __shfl(excl, o, 64);
+                        const int32_t r0 = __shfl(rs, o, 64);
+                        m[k] = (uint64_t)shfl64((int64_t)mymask, o);
+                        v[k] = vbase + (ok[k] ? colb[r0 + (e - ex)] : 0u);
+                    }
+                    brelax(a, v, m, ok);
+                }
+            }
+        }
+        wave_lds_sync();
+    }
+    if (lane == 0 && edges) atomicAdd(a.edges, edges);
+}
+
+__global__ __launch_bounds__(kBThreads) void bexpand_big_kernel(BArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned long long edges = 0;
+    int64_t before = 0;  // items of the processors before r, for a grid-wide stride
+    for (int32_t r = 0; r < a.P; ++r) {
+        const int64_t cap = a.qoff[r + 1] - a.qoff[r];
+        const int64_t queued = a.queue_count[r];
+        const int64_t count = queued < cap ? queued : cap;
+        const BItem *queue = a.queue + a.qoff[r];
+        const int64_t vbase = (int64_t)r * a.R;
+        int64_t first = (wave - before) % nwaves;
+        if (first < 0) first += nwaves;
+        before += count;
+        for (int64_t kk = first; kk < count; kk += nwaves) {
+            const BItem it = queue[kk];
+            const uint32_t *colb = a.col + a.col_base[it.block];
+            for (int32_t e0 = it.start; e0 < it.end; e0 += 64 * kBUnroll) {
+                int64_t v[kBUnroll];
+                uint64_t m[kBUnroll];
+                bool ok[kBUnroll];
+#pragma unroll
+                for (int k = 0; k < kBUnroll; ++k) {
+                    const int32_t e = e0 + 64 * k + lane;
+                    ok[k] = e < it.end;
+                    v[k] = vbase + (ok[k] ? colb[e] : 0u);
+                    m[k] = it.mask;
+                }
+                brelax(a, v, m, ok);
+            }
+            edges += (unsigned long long)(it.end - it.start);
+        }
+    }
+    if (lane == 0 && edges) atomicAdd(a.edges, edges);
+}
+
+struct BUpdateArgs {
+    uint64_t *vis;
+    uint64_t *nx;
+    uint64_t *f;       // [B][n / 64] planes of the new frontier
+    int32_t *level;    // [B][n]
+    int32_t next_level;
+    int32_t B;
+    int64_t n;
+    unsigned long long *root_count;  // [B]
+    unsigned long long *total;       // [1]
+    uint32_t *queue_count;           // [P], cleared for the next level
+    int32_t P;
+};
+
+__global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
+    __shared__ uint64_t tile[kBThreads / 64][kBTile][kMaxRoots];
+    __shared__ unsigned long long cnt[kMaxRoots];
+    const int lane = threadIdx.x & 63;
+    uint64_t(*tw)[kMaxRoots] = tile[threadIdx.x >> 6];
+    if (threadIdx.x < kMaxRoots) cnt[threadIdx.x] = 0;
+    if (blockIdx.x == 0)
+        for (int q = threadIdx.x; q < a.P; q += blockDim.x) a.queue_count[q] = 0;
+    __syncthreads();
+    const int64_t words = a.n / 64;
+    const int64_t ntiles = (words + kBTile - 1) / kBTile;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int t_st = lane % kBTile, r_st = lane / kBTile;
+    const int nsteps = (a.B + kBRootsPerOp - 1) / kBRootsPerOp;
+    unsigned long long mine = 0;  // lane r: new vertices of root r seen by this wave
+    for (int64_t tl = wave; tl < ntiles; tl += nwaves) {
+        const int64_t q0 = tl * kBTile;
+        for (int t = 0; t < kBTile; ++t) {
+            const int64_t q = q0 + t;
+            uint64_t plane = 0;
+            if (q < words) {
+                const int64_t v = (q << 6) + lane;
+                const uint64_t nxv = a.nx[v];
+                uint64_t nw = 0;
+                if (nxv) {
+                    a.nx[v] = 0;
+                    const uint64_t visv = a.vis[v];
+                    nw = nxv & ~visv;
+                    if (nw) a.vis[v] = visv | nw;
+                }
+                // lane r collects root r's frontier word: bit b = vertex q*64+b is new for r
+                for (uint64_t it = wave_or64(nw); it; it &= it - 1) {
+                    const int r = __ffsll((unsigned long long)it) - 1;
+                    const bool mine_r = (nw >> r) & 1;
+                    if (mine_r) a.level[(int64_t)r * a.n + v] = a.next_level;
+                    const uint64_t bal = __ballot(mine_r);
+                    if (lane == r) plane = bal;
+                }
+            }
+            tw[t][lane] = plane;
+            mine += (unsigned long long)__popcll(plane);
+        }
+        wave_lds_sync();
+        for (int s = 0; s < nsteps; ++s) {
+            const int r = r_st + kBRootsPerOp * s;
+            const int64_t q = q0 + t_st;
+            if (r < a.B && q < words) a.f[r * words + q] = tw[t_st][r];
+        }
+        wave_lds_sync();
+    }
+    if (lane < a.B && mine) atomicAdd(&cnt[lane], mine);
+    __syncthreads();
+    if (threadIdx.x < a.B && cnt[threadIdx.x]) {
+        atomicAdd(&a.root_count[threadIdx.x], cnt[threadIdx.x]);
+        atomicAdd(a.total, cnt[threadIdx.x]);
+    }
+}
+
+struct BSeedArgs {
+    uint64_t *vis;
+    uint64_t *nx;
+    uint64_t *view;
+    int64_t view_words;  // all planes
+    int32_t *level;
+    int64_t level_words;  // n_roots * n
+    int64_t n;
+};
+
+__global__ void bseed_fill_kernel(BSeedArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t top = a.view_words > a.level_words ? a.view_words : a.level_words;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < top; k += stride) {
+        if (k < a.n) {
+            a.vis[k] = 0;
+            a.nx[k] = 0;
+        }
+        if (k < a.view_words) a.view[k] = 0;
+        if (k < a.level_words) a.level[k] = -1;
+    }
+}
+
+// f(s) <- s for every root: known to every processor without a message.
+__global__ void bseed_root_kernel(BSeedArgs a, const int64_t *roots, int32_t B, int64_t R, int64_t W,
+                                  int32_t P, int64_t vplane, unsigned long long *root_count0,
+                                  unsigned long long *total0) {
+    const int r = threadIdx.x;
+    if (r >= B) return;
+    const int64_t s = roots[r];
+    const int64_t own = s / R, sl = s - own * R;
+    atomicOr((unsigned long long *)&a.vis[s], 1ull << r);
+    a.level[(int64_t)r * a.n + s] = 0;
+    for (int32_t i = 0; i < P; ++i)
+        a.view[r * vplane + ((int64_t)i * P + own) * W + (sl >> 6)] = 1ull << (sl & 63);
+    root_count0[r] = 1;
+    atomicAdd(total0, 1ull);
+}
+
+}  // namespace
+}  // namespace csbfs
+
+using namespace csbfs;
+
+struct csbfs_batch_engine {
+    const csbfs_graph *g = nullptr;
+    int32_t Bmax = 0, L = 0;
+    uint32_t flags = 0;
+    int64_t cap = 0, nseg = 0, nchunk = 0, Smax = 0;
+    uint64_t *vis = nullptr, *nx = nullptr, *f = nullptr, *view = nullptr, *arena = nullptr;
+    int32_t *seg_count = nullptr, *seg_first = nullptr;
+    int64_t *chunk_groups = nullptr;
+    BItem *queue = nullptr;
+    int64_t *qoff = nullptr;
+    uint32_t *qcount = nullptr;
+    int64_t *roots_dev = nullptr;
+    int32_t *status = nullptr;
+    void *counters_mem = nullptr;
+    size_t counters_bytes = 0;
+    unsigned long long *ctl = nullptr;    // [L+1] total frontier
+    unsigned long long *rootc = nullptr;  // [L+1][Bmax]
+    unsigned long long *edges = nullptr;  // [L+1]
+    unsigned long long *sbits = nullptr;  // [L+1][Smax]
+    unsigned long long *uwords = nullptr; // [L+1][Bmax * P]
+    int64_t *words = nullptr;             // [L+1][Smax]
+    unsigned long long *host_ctl = nullptr;  // pinned [2]
+    hipEvent_t count_ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> events;
+    std::vector<void *> allocs;
+    int32_t last_levels = 0, last_roots = 0;
+};
+
+namespace {
+
+void bengine_release(csbfs_batch_engine *e) {
+    (void)hipDeviceSynchronize();
+    for (void *p : e->allocs) (void)hipFree(p);
+    if (e->host_ctl) (void)hipHostFree(e->host_ctl);
+    for (hipEvent_t ev : e->count_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : e->events)
+        if (ev) (void)hipEventDestroy(ev);
+    delete e;
+}
+
+}  // namespace
+
+extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots, int32_t max_levels,
+                                         uint32_t flags, csbfs_batch_engine **out) {
+    if (!out) return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: out is NULL");
+    *out = nullptr;
+    if (!g) return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: graph is NULL");
+    if (max_roots < 1 || max_roots > kMaxRoots)
+        return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: max_roots outside [1, 64]");
+    if (max_levels < 1 || max_levels > 65536)
+        return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: max_levels outside [1, 65536]");
+    if (flags & ~(CSBFS_FLAG_TIMING | CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE))
+        return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: unsupported flag");
+    int rc = graph_device_check(g);
+    if (rc) return rc;
+    csbfs_batch_engine *e = new csbfs_batch_engine();
+    e->g = g;
+    e->Bmax = max_roots;
+    e->L = max_levels;
+    e->flags = flags;
+    const int64_t P = g->P, n = g->n, B = max_roots;
+    e->cap = wah_cap(g->R);
+    e->nseg = enc_segments(g->R);
+    e->nchunk = dec_chunks(g->R);
+    e->Smax = B * P * P;
+    const int64_t slots = (int64_t)max_levels + 1;
+    const int64_t arena_slots = (flags & CSBFS_FLAG_KEEP_STREAMS) ? slots : 1;
+    std::vector<int64_t> qoff(P + 1, 0);
+    for (int64_t r = 0; r < P; ++r) qoff[r + 1] = qoff[r] + g->big_items[r];
+    auto alloc = [&](void **p, size_t bytes) -> int {
+        hipError_t err = hipMalloc(p, bytes > 0 ? bytes : 1);
+        if (err != hipSuccess) return hip_fail(err, "hipMalloc", __FILE__, __LINE__);
+        e->allocs.push_back(*p);
+        return CSBFS_OK;
+    };
+#define BALLOC(ptr, bytes)                                                 \
+    do {                                                                   \
+        void *_p = nullptr;                                                \
+        int _rc = alloc(&_p, (bytes));                                     \
+        if (_rc) {                                                         \
+            bengine_release(e);                                            \
+            return _rc;                                                    \
+        }                                                                  \
+        ptr = reinterpret_cast<decltype(ptr)>(_p);                         \
+    } while (0)
+    BALLOC(e->vis, sizeof(uint64_t) * n);
+    BALLOC(e->nx, sizeof(uint64_t) * n);
+    BALLOC(e->f, sizeof(uint64_t) * B * (n / 64));
+    BALLOC(e->view, sizeof(uint64_t) * B * P * (n / 64));
+    BALLOC(e->arena, sizeof(uint64_t) * e->Smax * e->cap * arena_slots);
+    BALLOC(e->seg_count, sizeof(int32_t) * e->Smax * e->nseg);
+    BALLOC(e->seg_first, sizeof(int32_t) * e->Smax * e->nseg);
+    BALLOC(e->chunk_groups, sizeof(int64_t) * e->Smax * e->nchunk);
+    BALLOC(e->queue, sizeof(BItem) * (qoff[P] > 0 ? qoff[P] : 1));
+    BALLOC(e->qoff, sizeof(int64_t) * (P + 1));
+    BALLOC(e->qcount, sizeof(uint32_t) * P);
+    BALLOC(e->roots_dev, sizeof(int64_t) * B);
+    BALLOC(e->status, sizeof(int32_t));
+    const size_t cnt_bytes = sizeof(unsigned long long) * slots * (1 + B + 1 + e->Smax + B * P) +
+                             sizeof(int64_t) * slots * e->Smax;
+    BALLOC(e->counters_mem, cnt_bytes);
+#undef BALLOC
+    e->counters_bytes = cnt_bytes;
+    unsigned long long *c = (unsigned long long *)e->counters_mem;
+    e->ctl = c;
+    c += slots;
+    e->rootc = c;
+    c += slots * B;
+    e->edges = c;
+    c += slots;
+    e->sbits = c;
+    c += slots * e->Smax;
+    e->uwords = c;
+    c += slots * B * P;
+    e->words = (int64_t *)c;
+    hipError_t herr = hipMemcpy(e->qoff, qoff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice);
+    if (herr == hipSuccess) herr = hipMemset(e->view, 0, sizeof(uint64_t) * B * P * (n / 64));
+    if (herr == hipSuccess) herr = hipHostMalloc((void **)&e->host_ctl, 2 * sizeof(unsigned long long));
+    for (auto &ev : e->count_ev)
+        if (herr == hipSuccess) herr = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (herr == hipSuccess && (flags & CSBFS_FLAG_TIMING)) {
+        e->events.assign((size_t)max_levels * kBEvPerLevel, nullptr);
+        for (auto &ev : e->events)
+            if (herr == hipSuccess) herr = hipEventCreate(&ev);
+    }
+    if (herr != hipSuccess) {
+        bengine_release(e);
+        return hip_fail(herr, "csbfs_batch_engine_create", __FILE__, __LINE__);
+    }
+    *out = e;
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_batch_engine_free(csbfs_batch_engine *e) {
+    if (!e) return CSBFS_OK;
+    bengine_release(e);
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int32_t n_roots,
+                               int32_t *level, csbfs_level_stats *stats, int32_t stats_cap,
+                               int32_t *n_levels, void *stream) {
+    if (!e || !roots || !level || !n_levels || stats_cap < 0 || (stats_cap > 0 && !stats))
+        return fail(CSBFS_EINVAL, "csbfs_batch_bfs: null argument or negative stats_cap");
+    if (n_roots < 1 || n_roots > e->Bmax)
+        return fail(CSBFS_EINVAL, "csbfs_batch_bfs: n_roots outside [1, max_roots]");
+    const csbfs_graph *g = e->g;
+    for (int32_t r = 0; r < n_roots; ++r)
+        if (roots[r] < 0 || roots[r] >= g->n) return fail(CSBFS_ERANGE, "csbfs_batch_bfs: root outside [0, n)");
+    int rc = graph_device_check(g);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    const int64_t P = g->P, n = g->n, R = g->R, W = g->W, B = n_roots, Bm = e->Bmax;
+    const int64_t words = n / 64, vplane = P * words;
+    const bool timing = (e->flags & CSBFS_FLAG_TIMING) != 0;
+    const bool keep = (e->flags & CSBFS_FLAG_KEEP_STREAMS) != 0;
+
+    // a0: seed every root
+    CSBFS_HIP(hipMemsetAsync(e->counters_mem, 0, e->counters_bytes, st));
+    CSBFS_HIP(hipMemsetAsync(e->status, 0, sizeof(int32_t), st));
+    CSBFS_HIP(hipMemsetAsync(e->qcount, 0, sizeof(uint32_t) * P, st));
+    CSBFS_HIP(hipMemcpyAsync(e->roots_dev, roots, sizeof(int64_t) * B, hipMemcpyHostToDevice, st));
+    BSeedArgs sa{e->vis, e->nx, e->view, B * vplane, level, B * n, n};
+    const int64_t fill = B * n > B * vplane ? B * n : B * vplane;
+    hipLaunchKernelGGL(bseed_fill_kernel, dim3(grid_for(fill, 256, 16384)), dim3(256), 0, st, sa);
+    CSBFS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(bseed_root_kernel, dim3(1), dim3(64), 0, st, sa, (const int64_t *)e->roots_dev,
+                       (int32_t)B, R, W, (int32_t)P, vplane, e->rootc, e->ctl);
+    CSBFS_HIP(hipGetLastError());
+
+    BArgs ea{};
+    ea.view = e->view;
+    ea.vplane = vplane;
+    ea.B = (int32_t)B;
+    ea.row_ptr = g->row_ptr;
+    ea.col_base = g->col_base;
+    ea.col = g->col;
+    ea.vis = e->vis;
+    ea.nx = e->nx;
+    ea.queue = e->queue;
+    ea.qoff = e->qoff;
+    ea.queue_count = e->qcount;
+    ea.R = R;
+    ea.W = W;
+    ea.P = (int32_t)P;
+    ea.status = e->status;
+    const unsigned grid = 2048;
+
+    WahBatch wb{};
+    wb.bits_base = e->f;
+    wb.mask_base = (e->flags & CSBFS_FLAG_NO_SIEVE) ? nullptr : g->dir;
+    wb.nbits = R;
+    wb.words_per_piece = W;
+    wb.cap = e->cap;
+    wb.P = (int32_t)P;
+    wb.planes = (int32_t)B;
+    wb.bits_plane_stride = words;
+    wb.dst_plane_stride = vplane;
+    wb.seg_count = e->seg_count;
+    wb.seg_first = e->seg_first;
+    wb.nseg = e->nseg;
+    wb.chunk_groups = e->chunk_groups;
+    wb.nchunk = e->nchunk;
+    wb.dst_base = e->view;
+    wb.status = e->status;
+
+    auto slot = [&](int64_t k) { return k < e->L ? k : (int64_t)e->L; };
+    auto enqueue_iter = [&](int64_t j) -> int {
+        const int64_t sj = slot(j), sn = slot(j + 1);
+        if (j + 1 >= e->L) {
+            const int64_t Lz = e->L;
+            CSBFS_HIP(hipMemsetAsync(e->ctl + Lz, 0, sizeof(unsigned long long), st));
+            CSBFS_HIP(hipMemsetAsync(e->rootc + Lz * Bm, 0, sizeof(unsigned long long) * Bm, st));
+            CSBFS_HIP(hipMemsetAsync(e->edges + Lz, 0, sizeof(unsigned long long), st));
+            CSBFS_HIP(hipMemsetAsync(e->sbits + Lz * e->Smax, 0, sizeof(unsigned long long) * e->Smax, st));
+            CSBFS_HIP(hipMemsetAsync(e->uwords + Lz * Bm * P, 0, sizeof(unsigned long long) * Bm * P, st));
+        }
+        hipEvent_t *evp = (timing && j >= 1 && j - 1 < e->L) ? &e->events[(size_t)(j - 1) * kBEvPerLevel] : nullptr;
+        hipEvent_t *ev = (timing && j < e->L) ? &e->events[(size_t)j * kBEvPerLevel] : nullptr;
+        if (j >= 1) {
+            wb.out_base = e->arena + (keep ? sj : 0) * e->Smax * e->cap;
+            wb.n_words = e->words + sj * e->Smax;
+            wb.stat_sieved_bits = e->sbits + sj * e->Smax;
+            wb.stat_unsieved_words = e->uwords + sj * Bm * P;
+            int r2 = launch_wah_encode(wb, st);
+            if (r2) return r2;
+            if (evp) CSBFS_HIP(hipEventRecord(evp[3], st));
+            r2 = launch_wah_decode(wb, st);
+            if (r2) return r2;
+            if (evp) CSBFS_HIP(hipEventRecord(evp[4], st));
+        }
+        if (ev) CSBFS_HIP(hipEventRecord(ev[0], st));
+        ea.edges = e->edges + sj;
+        hipLaunchKernelGGL(bexpand_kernel, dim3(grid), dim3(kBThreads), 0, st, ea);
+        CSBFS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(bexpand_big_kernel, dim3(grid), dim3(kBThreads), 0, st, ea);
+        CSBFS_HIP(hipGetLastError());
+        if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
+        BUpdateArgs ua{e->vis, e->nx, e->f, level, (int32_t)(j + 1), (int32_t)B, n,
+                       e->rootc + sn * Bm, e->ctl + sn, e->qcount, (int32_t)P};
+        hipLaunchKernelGGL(bupdate_kernel, dim3(grid_for((words + kBTile - 1) / kBTile, kBThreads / 64, 2048)), dim3(kBThreads), 0, st, ua);
+        CSBFS_HIP(hipGetLastError());
+        if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
+        const int hs = (int)((j + 1) & 1);
+        CSBFS_HIP(hipMemcpyAsync(e->host_ctl + hs, e->ctl + sn, sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, st));
+        CSBFS_HIP(hipEventRecord(e->count_ev[hs], st));
+        return CSBFS_OK;
+    };
+
+    rc = enqueue_iter(0);
+    if (rc) return rc;
+    int64_t k = 0;
+    for (;; ++k) {
+        rc = enqueue_iter(k + 1);
+        if (rc) return rc;
+        const int hs = (int)((k + 1) & 1);
+        CSBFS_HIP(hipEventSynchronize(e->count_ev[hs]));
+        if (e->host_ctl[hs] == 0) break;
+    }
+    const int64_t nl = k + 1;
+    *n_levels = (int32_t)(nl < INT32_MAX ? nl : INT32_MAX);
+    e->last_levels = *n_levels;
+    e->last_roots = (int32_t)B;
+
+    int32_t hstatus = 0;
+    CSBFS_HIP(hipMemcpyAsync(&hstatus, e->status, sizeof(hstatus), hipMemcpyDeviceToHost, st));
+    const int64_t have = nl < e->L ? nl : e->L;
+    const int64_t want = stats_cap < have ? stats_cap : have;
+    std::vector<unsigned long long> rootc, ed, sb, uw;
+    std::vector<int64_t> wd;
+    if (want > 0) {
+        rootc.resize(want * Bm);
+        ed.resize(want);
+        sb.resize(want * e->Smax);
+        uw.resize(want * Bm * P);
+        wd.resize(want * e->Smax);
+        CSBFS_HIP(hipMemcpyAsync(rootc.data(), e->rootc, sizeof(unsigned long long) * want * Bm, hipMemcpyDeviceToHost, st));
+        CSBFS_HIP(hipMemcpyAsync(ed.data(), e->edges, sizeof(unsigned long long) * want, hipMemcpyDeviceToHost, st));
+        CSBFS_HIP(hipMemcpyAsync(sb.data(), e->sbits, sizeof(unsigned long long) * want * e->Smax, hipMemcpyDeviceToHost, st));
+        CSBFS_HIP(hipMemcpyAsync(uw.data(), e->uwords, sizeof(unsigned long long) * want * Bm * P, hipMemcpyDeviceToHost, st));
+        CSBFS_HIP(hipMemcpyAsync(wd.data(), e->words, sizeof(int64_t) * want * e->Smax, hipMemcpyDeviceToHost, st));
+    }
+    CSBFS_HIP(hipStreamSynchronize(st));
+    if (hstatus != 0) {
+        if (hstatus == 1) return fail(CSBFS_ECORRUPT, "csbfs_batch_bfs: a stream failed validation while decoding");
+        return fail(CSBFS_ECORRUPT, "csbfs_batch_bfs: internal consistency check failed");
+    }
+    for (int64_t lv = 0; lv < want; ++lv) {
+        csbfs_level_stats &s = stats[lv];
+        s = csbfs_level_stats{};
+        s.edges = (int64_t)ed[lv];
+        std::vector<int64_t> send(P, 0), recv(P, 0);
+        for (int64_t r = 0; r < B; ++r) {
+            const int64_t fr = (int64_t)rootc[lv * Bm + r];
+            if (fr == 0) continue;
+            s.frontier += fr;
+            if (lv == 0) {
+                s.view_bits += P;
+                continue;
+            }
+            s.unsieved_bits += (P - 1) * fr;
+            s.raw_bytes += P * (P - 1) * 8 * W;
+            for (int64_t i = 0; i < P; ++i) {
+                s.wah_unsieved_bytes += 8 * (P - 1) * (int64_t)uw[lv * Bm * P + r * P + i];
+                for (int64_t j = 0; j < P; ++j) {
+                    const int64_t sidx = lv * e->Smax + (r * P + i) * P + j;
+                    s.view_bits += (int64_t)sb[sidx];
+                    if (i == j) {
+                        s.self_bytes += 8 * wd[sidx];
+                        continue;
+                    }
+                    s.sieved_bits += (int64_t)sb[sidx];
+                    s.wah_sieved_bytes += 8 * wd[sidx];
+                    send[i] += 8 * wd[sidx];
+                    recv[j] += 8 * wd[sidx];
+                }
+            }
+        }
+        for (int64_t i = 0; i < P; ++i) s.max_rank_bytes = std::max(s.max_rank_bytes, send[i] + recv[i]);
+    }
+    if (timing) {
+        for (int64_t lv = 0; lv < nl && lv < e->L; ++lv) {
+            hipEvent_t *ev = &e->events[(size_t)lv * kBEvPerLevel];
+            float a = 0, b = 0;
+            CSBFS_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+            CSBFS_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
+            if (lv < want) {
+                stats[lv].ms_expand = a;
+                stats[lv].ms_update = b;
+            }
+            if (lv + 1 < nl && lv + 1 < want) {
+                float c = 0, d = 0;
+                CSBFS_HIP(hipEventElapsedTime(&c, ev[2], ev[3]));
+                CSBFS_HIP(hipEventElapsedTime(&d, ev[3], ev[4]));
+                stats[lv + 1].ms_compress = c;
+                stats[lv + 1].ms_decode = d;
+            }
+        }
+    }
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_batch_stream_words(const csbfs_batch_engine *e, int32_t *words, int32_t cap_levels) {
+    if (!e || !words || cap_levels < 0) return fail(CSBFS_EINVAL, "csbfs_batch_stream_words: bad argument");
+    const int64_t P = e->g->P, B = e->last_roots, Bm = e->Bmax;
+    const int64_t lv_have = std::min<int64_t>(e->L, e->last_levels);
+    std::vector<int64_t> wd((size_t)(lv_have > 0 ? lv_have : 1) * e->Smax);
+    std::vector<unsigned long long> rc((size_t)(lv_have > 0 ? lv_have : 1) * Bm);
+    if (lv_have > 0) {
+        CSBFS_HIP(hipMemcpy(wd.data(), e->words, sizeof(int64_t) * lv_have * e->Smax, hipMemcpyDeviceToHost));
+        CSBFS_HIP(hipMemcpy(rc.data(), e->rootc, sizeof(unsigned long long) * lv_have * Bm, hipMemcpyDeviceToHost));
+    }
+    for (int64_t lv = 0; lv < cap_levels; ++lv)
+        for (int64_t r = 0; r < B; ++r)
+            for (int64_t s = 0; s < P * P; ++s) {
+                const bool live = lv > 0 && lv < lv_have && rc[lv * Bm + r] > 0;
+                words[(lv * B + r) * P * P + s] = live ? (int32_t)wd[lv * e->Smax + r * P * P + s] : 0;
+            }
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_batch_copy_stream(const csbfs_batch_engine *e, int32_t k, int32_t r, int32_t i,
+                                       int32_t j, uint64_t *dst, int64_t cap_words, int64_t *n_words_out,
+                                       void *stream) {
+    if (!e || !dst || !n_words_out) return fail(CSBFS_EINVAL, "csbfs_batch_copy_stream: null argument");
+    if (!(e->flags & CSBFS_FLAG_KEEP_STREAMS))
+        return fail(CSBFS_EINVAL, "csbfs_batch_copy_stream: engine lacks CSBFS_FLAG_KEEP_STREAMS");
+    const int64_t P = e->g->P;
+    if (k < 0 || k >= e->L || k >= e->last_levels || r < 0 || r >= e->last_roots || i < 0 || i >= P ||
+        j < 0 || j >= P)
+        return fail(CSBFS_EINVAL, "csbfs_batch_copy_stream: level, root or processor out of range");
+    const int64_t s = ((int64_t)r * P + i) * P + j;
+    hipStream_t st = as_stream(stream);
+    int64_t nw = 0;
+    unsigned long long fr = 0;
+    CSBFS_HIP(hipMemcpyAsync(&fr, e->rootc + (int64_t)k * e->Bmax + r, sizeof(fr), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipMemcpyAsync(&nw, e->words + (int64_t)k * e->Smax + s, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    if (k == 0 || fr == 0) nw = 0;  // no message carries level 0 or an empty frontier
+    *n_words_out = nw;
+    if (nw > cap_words) return fail(CSBFS_ENOSPACE, "csbfs_batch_copy_stream: dst too small");
+    if (nw > 0)
+        CSBFS_HIP(hipMemcpyAsync(dst, e->arena + ((int64_t)k * e->Smax + s) * e->cap, sizeof(uint64_t) * nw,
+                                 hipMemcpyDeviceToDevice, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    return CSBFS_OK;
+}

@@ -54,11 +54,13 @@ inline int64_t dec_chunks(int64_t nbits) { return (wah_cap(nbits) + kDecChunk - 
 
 // ---------------------------------------------------------- WAH batches ---
 //
-// A batch holds S = P * P streams; stream s = i * P + j carries the piece of
-// processor i (bits_base + i * words_per_piece) sieved with the directory
-// vector V_{j,i} (mask_base + (j * P + i) * words_per_piece, or no mask), is
-// written to out_base + s * cap, and is decoded into dst_base + (j * P + i) *
-// words_per_piece (the receiver j's view of the range of i).
+// A batch holds S = planes * P * P streams (one plane per search root; one
+// plane for a single search). Stream s = (r * P + i) * P + j carries the
+// piece of processor i in plane r (bits_base + r * bits_plane_stride + i *
+// words_per_piece) sieved with the directory vector V_{j,i} (mask_base +
+// (j * P + i) * words_per_piece, or no mask), is written to out_base + s *
+// cap, and is decoded into dst_base + r * dst_plane_stride + (j * P + i) *
+// words_per_piece (receiver j's view of the range of i, plane r).
 
 struct WahBatch {
     const uint64_t *bits_base;
@@ -69,6 +71,9 @@ struct WahBatch {
     int64_t words_per_piece;    // ceil(nbits / 64)
     int64_t cap;                // words per stream slot
     int32_t P;
+    int32_t planes;             // 0 or 1 for one search
+    int64_t bits_plane_stride;
+    int64_t dst_plane_stride;
     // encoder scratch: per (stream, segment) flag counts and first flagged group
     int32_t *seg_count;         // device [S * nseg]
     int32_t *seg_first;         // device [S * nseg]
@@ -80,8 +85,20 @@ struct WahBatch {
     int32_t *status;            // device [1], non-zero on a corrupt stream
     // optional statistics (device, nullable)
     unsigned long long *stat_sieved_bits;    // [S]
-    unsigned long long *stat_unsieved_words; // [P]: words of WAH(piece_i), no mask
+    unsigned long long *stat_unsieved_words; // [planes * P]: words of WAH(piece_i), no mask
 };
+
+// Stream s of a batch: plane r, sender i, receiver j.
+struct StreamIdx {
+    int64_t r, i, j;
+};
+__host__ __device__ inline StreamIdx stream_idx(int64_t s, int32_t P) {
+    const int64_t pp = (int64_t)P * P, s2 = s % pp;
+    return StreamIdx{s / pp, s2 / P, s2 % P};
+}
+inline int64_t batch_streams(const WahBatch &b) {
+    return (int64_t)(b.planes > 1 ? b.planes : 1) * b.P * b.P;
+}
 
 int launch_wah_encode(const WahBatch &b, hipStream_t stream);
 int launch_wah_decode(const WahBatch &b, hipStream_t stream);

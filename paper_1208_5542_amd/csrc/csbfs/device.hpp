@@ -1,0 +1,88 @@
+// Wavefront helpers shared by the search kernels (not installed).
+#pragma once
+
+#include "common.hpp"
+
+namespace csbfs {
+
+__device__ __forceinline__ int wave_incl_scan_i32(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Owner lane of slot x: the largest lane L whose exclusive prefix excl[L] is
+// at most x (excl non-decreasing over the lanes, excl[0] = 0).
+__device__ __forceinline__ int owner_lane(int32_t excl, int32_t x) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int probe = lo + step;
+        const int32_t ex = __shfl(excl, probe < 64 ? probe : 63, 64);
+        if (probe < 64 && ex <= x) lo = probe;
+    }
+    return lo;
+}
+
+// Position of the r-th (0-based) set bit of w; w has more than r set bits.
+__device__ __forceinline__ int select_bit(uint64_t w, int r) {
+    int pos = 0;
+    int c = __popc((uint32_t)w);
+    if (r >= c) {
+        r -= c;
+        w >>= 32;
+        pos += 32;
+    }
+    uint32_t x = (uint32_t)w;
+    c = __popc(x & 0xFFFFu);
+    if (r >= c) {
+        r -= c;
+        x >>= 16;
+        pos += 16;
+    }
+    c = __popc(x & 0xFFu);
+    if (r >= c) {
+        r -= c;
+        x >>= 8;
+        pos += 8;
+    }
+    c = __popc(x & 0xFu);
+    if (r >= c) {
+        r -= c;
+        x >>= 4;
+        pos += 4;
+    }
+    c = __popc(x & 0x3u);
+    if (r >= c) {
+        r -= c;
+        x >>= 2;
+        pos += 2;
+    }
+    if (r >= (int)(x & 1u)) pos += 1;
+    return pos;
+}
+
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
+    const int32_t lo = __shfl((int32_t)(uint32_t)v, src, 64);
+    const int32_t hi = __shfl((int32_t)(v >> 32), src, 64);
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v |= (uint64_t)shfl64((int64_t)v, (threadIdx.x & 63) ^ d);
+    return v;
+}
+
+inline unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace csbfs

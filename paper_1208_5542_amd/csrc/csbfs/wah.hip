@@ -150,8 +150,9 @@ __device__ __forceinline__ SegGeom seg_geom(const WahBatch &b, int64_t seg) {
 // Stage the segment's words (sieved, and optionally unsieved) into LDS.
 __device__ __forceinline__ void stage(const WahBatch &b, int64_t s, const SegGeom &g, uint64_t *sw,
                                       uint64_t *su) {
-    const int64_t i = s / b.P, j = s % b.P;
-    const uint64_t *bits = b.bits_base + i * b.words_per_piece;
+    const StreamIdx x = stream_idx(s, b.P);
+    const int64_t i = x.i, j = x.j;
+    const uint64_t *bits = b.bits_base + x.r * b.bits_plane_stride + i * b.words_per_piece;
     const uint64_t *mask = b.mask_base ? b.mask_base + (j * b.P + i) * b.words_per_piece : nullptr;
     const int tail = (int)(b.nbits & 63);
     for (int64_t k = threadIdx.x; k < g.nload; k += blockDim.x) {
@@ -200,7 +201,8 @@ __global__ __launch_bounds__(kEncThreads) void wah_enc_count(WahBatch b) {
     __shared__ uint64_t su[kEncLds];
     const int64_t seg = blockIdx.x;
     const int64_t s = blockIdx.y;
-    const int64_t i = s / b.P, j = s % b.P;
+    const StreamIdx x = stream_idx(s, b.P);
+    const int64_t i = x.i, j = x.j;
     const bool unsieved = b.stat_unsieved_words && i == j;
     const SegGeom g = seg_geom(b, seg);
     stage(b, s, g, sw, unsieved ? su : nullptr);
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(kEncThreads) void wah_enc_count(WahBatch b) {
         if (b.stat_sieved_bits && tot) atomicAdd(&b.stat_sieved_bits[s], (unsigned long long)tot);
         if (unsieved) {
             const int words = ucnt + (g.last && g.r > 0 ? 1 : 0);
-            if (words) atomicAdd(&b.stat_unsieved_words[i], (unsigned long long)words);
+            if (words) atomicAdd(&b.stat_unsieved_words[x.r * b.P + i], (unsigned long long)words);
         }
     }
 }
@@ -364,13 +366,14 @@ __global__ __launch_bounds__(kDecThreads) void wah_dec_count(WahBatch b) {
 __global__ __launch_bounds__(kDecThreads) void wah_dec_scatter(WahBatch b) {
     const int64_t c = blockIdx.x;
     const int64_t s = blockIdx.y;
-    const int64_t i = s / b.P, j = s % b.P;
+    const StreamIdx si = stream_idx(s, b.P);
+    const int64_t i = si.i, j = si.j;
     const int64_t G = b.nbits / kGroupBits;
     const int64_t r = b.nbits - G * kGroupBits;
     const int64_t nw = stream_words(b, s);
     const int64_t nreg = nw - (r > 0 ? 1 : 0);
     const uint64_t *words = b.out_base + s * b.cap;
-    uint64_t *dst = b.dst_base + (j * b.P + i) * b.words_per_piece;
+    uint64_t *dst = b.dst_base + si.r * b.dst_plane_stride + (j * b.P + i) * b.words_per_piece;
     const int64_t w0 = c * kDecChunk;
 
     if (c == 0 && threadIdx.x == 0) {
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(kDecThreads) void wah_dec_scatter(WahBatch b) {
 }  // namespace
 
 int launch_wah_encode(const WahBatch &b, hipStream_t stream) {
-    const int64_t S = (int64_t)b.P * b.P;
+    const int64_t S = batch_streams(b);
     dim3 grid((unsigned)b.nseg, (unsigned)S);
     hipLaunchKernelGGL(wah_enc_count, grid, dim3(kEncThreads), 0, stream, b);
     CSBFS_HIP(hipGetLastError());
@@ -441,7 +444,7 @@ int launch_wah_encode(const WahBatch &b, hipStream_t stream) {
 }
 
 int launch_wah_decode(const WahBatch &b, hipStream_t stream) {
-    const int64_t S = (int64_t)b.P * b.P;
+    const int64_t S = batch_streams(b);
     dim3 grid((unsigned)b.nchunk, (unsigned)S);
     hipLaunchKernelGGL(wah_dec_count, grid, dim3(kDecThreads), 0, stream, b);
     CSBFS_HIP(hipGetLastError());
