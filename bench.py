@@ -45,6 +45,10 @@ def parse():
                     help="evaluation of each level's product (results are identical)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-workload", default="rmat24_p4",
+                    help="workload of the batched comparison (64 roots in one search)")
+    ap.add_argument("--batch-reps", type=int, default=3, help="timed batches")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
     ap.add_argument("--json-out", default=None, help="also write a detailed report here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
@@ -121,6 +125,80 @@ def cpu_baseline(n, src, dst, p, roots, budget_s):
         "queue_bfs_gteps": round(q_done / q_inv / 1e9, 4),
         "queue_bfs_note": "serial FIFO-queue BFS + max-parent pass on the same roots, one thread",
     }
+
+
+def batched_section(args):
+    """64 roots searched together by the batched engine against the same 64
+    roots searched one at a time, on one resident graph: aggregate GTEPS
+    (sum over roots of the reached component's tuples / time) of both, and
+    whether every root's levels agree between the two engines."""
+    import torch
+
+    from paper_1208_5542_amd import csbfs, inputs
+
+    wl = inputs.WORKLOADS[args.batched_workload]
+    n, p = wl.n, wl.p
+    t = time.perf_counter()
+    src, dst = wl.tuples()
+    roots = [int(r) for r in wl.roots(src, dst, 64)]
+    g = csbfs.Graph(torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), n, p)
+    del src, dst
+    torch.cuda.synchronize()
+    log(f"[bench] batched: graph {wl.name} built in {time.perf_counter() - t:.1f}s")
+    B = len(roots)
+    beng = csbfs.BatchEngine(g, max_roots=64, max_levels=256, flags=csbfs.FLAG_TIMING)
+    seng = csbfs.Engine(g, max_levels=256, flags=csbfs.FLAG_TIMING)
+    blevel = torch.empty((B, n), dtype=torch.int32, device="cuda")
+    level = torch.empty(n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    beng.bfs(roots, blevel)
+    seng.bfs(roots[0], level, parent)
+    torch.cuda.synchronize()
+    bms, bstats = [], None
+    for _ in range(max(args.batch_reps, 1)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        res = beng.bfs(roots, blevel)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bms.append(e0.elapsed_time(e1))
+        bstats = res.stats
+    m = [g.traversed_tuples(blevel[b]) for b in range(B)]
+    sms, match = [], True
+    for b, r in enumerate(roots):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        seng.bfs(r, level, parent)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sms.append(e0.elapsed_time(e1))
+        match = match and bool(torch.equal(level, blevel[b]))
+    bt = min(bms) / 1e3
+    st = sum(sms) / 1e3
+    split = {k: round(sum(s[f"ms_{k}"] for s in bstats), 4)
+             for k in ("expand", "update", "compress", "decode")}
+    raw = sum(s["raw_bytes"] for s in bstats)
+    wah = sum(s["wah_sieved_bytes"] for s in bstats)
+    out = {
+        "workload": wl.name, "scale": wl.scale, "p": p, "roots": B,
+        "levels": res.n_levels,
+        "batched_ms": round(min(bms), 3), "batched_ms_all": [round(x, 3) for x in bms],
+        "batched_gteps": round(sum(m) / bt / 1e9, 4),
+        "sequential_ms": round(sum(sms), 3),
+        "sequential_gteps": round(sum(m) / st / 1e9, 4),
+        "sequential_hmean_gteps": round(B / sum((t / 1e3) / mm for t, mm in zip(sms, m)) / 1e9, 4),
+        "speedup": round(st / bt, 3),
+        "levels_match_single_root": match,
+        "time_split_ms": split,
+        "compression_ratio": round(raw / max(wah, 1), 3),
+        "edges_scanned": sum(s["edges"] for s in bstats),
+    }
+    log(f"[bench] batched {out['batched_gteps']} GTEPS vs sequential {out['sequential_gteps']} "
+        f"(x{out['speedup']}), levels match: {match}")
+    del beng, seng, g
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -253,6 +331,10 @@ def main():
                      "avg_launch_ms": round(exp_ms / max(exp_launches, 1), 5)},
         "wall_s": round(wall, 3),
     }
+    if not args.no_batched:
+        del eng, g, level, parent
+        torch.cuda.empty_cache()
+        out["batched"] = batched_section(args)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(n, src, dst, p, roots[args.warmup:], args.cpu_seconds)

@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define CSBFS_VERSION 10000 /* 1.0.0 */
+#define CSBFS_VERSION 10100 /* 1.1.0 */
 
 #define CSBFS_OK 0
 #define CSBFS_EINVAL (-1)    /* null pointer, bad size or bad flag */
@@ -153,13 +153,27 @@ typedef struct csbfs_engine csbfs_engine;
 #define CSBFS_FLAG_TIMING 1u       /* record per-kernel times into the level stats */
 #define CSBFS_FLAG_KEEP_STREAMS 2u /* keep every level's WAH streams for copy-out */
 #define CSBFS_FLAG_NO_SIEVE 4u     /* all-ones directory: Alg. 2 messages (no sieve) */
-/* The (select, max) product of a level is evaluated either by pushing every
- * source into parent[] with atomicMax ("sparse", the default) or by marking
- * targets seen and letting each new vertex pull its highest frontier
- * neighbour from its sorted rows ("dense"); both give identical results.
- * These flags force one evaluation for every level. */
+/* The (select, max) product t_i = sum_j A_{i,j} (x) f_{i,j} of a level has
+ * three exact evaluations, all giving identical level[] and parent[]:
+ *   top-down ("sparse"): every frontier source in the views pushes itself
+ *       into parent[] of its unvisited neighbours with atomicMax;
+ *   bottom-up: every unvisited vertex scans its rows, sorted by decreasing
+ *       id, and stops at the first neighbour set in its views (the highest
+ *       one); the direction-optimizing search of Beamer et al., which the
+ *       paper names as future work (Sec. VIII);
+ *   dense: the push only marks targets seen, then each new vertex pulls its
+ *       parent as in bottom-up.
+ * By default each level is top-down or bottom-up, chosen on the device from
+ * the frontier (see csbfs_engine_set_direction). These flags force one
+ * evaluation for every level. */
 #define CSBFS_FLAG_SPARSE_ONLY 8u
 #define CSBFS_FLAG_DENSE_ONLY 16u
+#define CSBFS_FLAG_BOTTOM_UP_ONLY 32u
+
+/* Level directions reported in csbfs_level_stats.direction. */
+#define CSBFS_DIR_TOP_DOWN 0
+#define CSBFS_DIR_BOTTOM_UP 1
+#define CSBFS_DIR_DENSE 2
 
 /*
  * Allocate the workspace of Algorithm 3 for graph g: visited vector pi,
@@ -172,6 +186,18 @@ typedef struct csbfs_engine csbfs_engine;
 int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags,
                         csbfs_engine **out);
 
+/*
+ * Parameters of the per-level direction choice (Beamer, Asanovic and
+ * Patterson's rule). After the update that produced f^{k+1}, with m_f the
+ * adjacency entries of f^{k+1} and m_u those of the still unvisited
+ * vertices: a top-down search turns bottom-up when m_f * alpha > m_u; a
+ * bottom-up search turns top-down again when |f^{k+1}| * beta < n and the
+ * frontier shrank. Level 0 is top-down. alpha <= 0 keeps every level
+ * top-down. Takes effect at the next csbfs_bfs. Errors: EINVAL (NULL
+ * engine, beta <= 0 or a NaN).
+ */
+int csbfs_engine_set_direction(csbfs_engine *e, float alpha, float beta);
+
 /* Release an engine. NULL is accepted. Blocking. */
 int csbfs_engine_free(csbfs_engine *e);
 
@@ -179,7 +205,9 @@ int csbfs_engine_free(csbfs_engine *e);
  * messages carrying it (which exist for k >= 1; level 0 is seeded). */
 typedef struct csbfs_level_stats {
     int64_t frontier;           /* |f^k|; 1 at level 0 */
-    int64_t edges;              /* adjacency entries scanned when expanding f^k */
+    int64_t edges;              /* adjacency entries read when expanding f^k (top-down:
+                                   the rows of its sources; bottom-up: the entries the
+                                   unvisited vertices read before their first hit) */
     int64_t view_bits;          /* ones over all p x p views the expansion of f^k reads:
                                    sum over all i, j of ones(f_i^k . V_{j,i}); p at level 0 */
     int64_t sieved_bits;        /* sum over i != j of ones(f_i^k . V_{j,i}) */
@@ -189,10 +217,13 @@ typedef struct csbfs_level_stats {
     int64_t wah_sieved_bytes;   /* sum over i != j of 8 |WAH(f_i^k . V_{j,i})|: Alg. 3 bytes */
     int64_t self_bytes;         /* sum over i of 8 |WAH(f_i^k . V_{i,i})| (never sent) */
     int64_t max_rank_bytes;     /* max over i of Alg. 3 bytes sent plus received by P_i */
-    float ms_expand;            /* expansion of f^k (both expansion kernels) (TIMING) */
+    int64_t pulled;             /* bottom-up: unvisited vertices that scanned their rows */
+    float ms_expand;            /* expansion of f^k (every expansion kernel) (TIMING) */
     float ms_update;            /* mask, visit update and reduction that follow it (TIMING) */
     float ms_compress;          /* sieve + WAH encode of the f^k messages (TIMING) */
     float ms_decode;            /* decode/merge of the f^k messages (TIMING) */
+    int32_t direction;          /* CSBFS_DIR_* used to expand f^k */
+    int32_t reserved;
 } csbfs_level_stats;
 
 /*

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libcsbfs.so")
 
 OK, EINVAL, ERANGE, ENOSPACE, EHIP, EOVERFLOW, ECORRUPT = 0, -1, -2, -3, -4, -5, -6
 FLAG_TIMING, FLAG_KEEP_STREAMS, FLAG_NO_SIEVE, FLAG_SPARSE_ONLY, FLAG_DENSE_ONLY = 1, 2, 4, 8, 16
+FLAG_BOTTOM_UP_ONLY = 32
+DIR_TOP_DOWN, DIR_BOTTOM_UP, DIR_DENSE = 0, 1, 2
 
 _lib = None
 
@@ -39,9 +41,10 @@ class LevelStats(ctypes.Structure):
                 ("view_bits", ctypes.c_int64), ("sieved_bits", ctypes.c_int64), ("unsieved_bits", ctypes.c_int64),
                 ("raw_bytes", ctypes.c_int64), ("wah_unsieved_bytes", ctypes.c_int64),
                 ("wah_sieved_bytes", ctypes.c_int64), ("self_bytes", ctypes.c_int64),
-                ("max_rank_bytes", ctypes.c_int64), ("ms_expand", ctypes.c_float),
-                ("ms_update", ctypes.c_float), ("ms_compress", ctypes.c_float),
-                ("ms_decode", ctypes.c_float)]
+                ("max_rank_bytes", ctypes.c_int64), ("pulled", ctypes.c_int64),
+                ("ms_expand", ctypes.c_float), ("ms_update", ctypes.c_float),
+                ("ms_compress", ctypes.c_float), ("ms_decode", ctypes.c_float),
+                ("direction", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -70,6 +73,7 @@ def lib():
         "csbfs_count_traversed_tuples": ([vp, vp, ctypes.POINTER(i64), vp], ctypes.c_int),
         "csbfs_engine_create": ([vp, i32, u32, ctypes.POINTER(vp)], ctypes.c_int),
         "csbfs_engine_free": ([vp], ctypes.c_int),
+        "csbfs_engine_set_direction": ([vp, ctypes.c_float, ctypes.c_float], ctypes.c_int),
         "csbfs_bfs": ([vp, i64, vp, vp, ctypes.POINTER(LevelStats), i32, ctypes.POINTER(i32), vp],
                       ctypes.c_int),
         "csbfs_engine_stream_words": ([vp, vp, i32], ctypes.c_int),
@@ -210,6 +214,10 @@ class Engine:
             self.close()
         except Exception:
             pass
+
+    def set_direction(self, alpha: float, beta: float):
+        """Parameters of the per-level top-down / bottom-up choice."""
+        _check(lib().csbfs_engine_set_direction(self._h, alpha, beta), "csbfs_engine_set_direction")
 
     def bfs(self, root: int, level: torch.Tensor | None = None, parent: torch.Tensor | None = None,
             stream=None, with_stats: bool = True) -> BfsResult:

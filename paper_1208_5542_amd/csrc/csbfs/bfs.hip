@@ -7,15 +7,22 @@
 //
 //   expand   t_i = sum_j A_{i,j} (x) f_{i,j} over the (select, max) semiring
 //            (Sec. III.A: the highest-labelled frontier neighbour wins).
-//            Top-down: every set bit u of view (i, j) is a source whose row
-//            in block (i, j) is pushed to its targets v in R_i. Two exact
-//            evaluations of the same product, chosen per level:
-//              sparse: an unvisited v takes u by atomicMax into parent[v],
-//                      the first writer sets S bit v;
-//              dense:  the push only sets S bits (a bitmap small enough to
-//                      stay in L2); then every new v pulls its parent: the
-//                      rows of v are sorted by decreasing id, so the first
-//                      neighbour found in the views is the maximum.
+//            Three exact evaluations of the same product:
+//              top-down (sparse): every set bit u of view (i, j) is a source
+//                      whose row in block (i, j) is pushed to its targets v
+//                      in R_i; an unvisited v takes u by atomicMax into
+//                      parent[v];
+//              bottom-up: every unvisited v of R_i scans its rows, sorted by
+//                      decreasing id, block j = P-1 down to 0, and stops at
+//                      the first neighbour set in view (i, j): the maximum;
+//              dense:  a top-down push that only sets S bits (a bitmap small
+//                      enough to stay in L2), then every new v pulls its
+//                      parent as in bottom-up.
+//            By default each level is top-down or bottom-up: after the
+//            update, a one-thread kernel applies Beamer's rule to the new
+//            frontier's size and adjacency entries and stores the direction
+//            of the next level on the device, where every expansion kernel
+//            reads it (the kernels not chosen return at once).
 //   update   t_i = S_i & ~pi_i; pi_i = S_i; f_i = t_i; level[v] = k + 1; the
 //            frontier size is reduced into a counter that the host reads;
 //            the views are cleared for the next level's messages.
@@ -38,6 +45,9 @@ constexpr int kUpdThreads = 256;
 constexpr int kPullThreads = 256;
 constexpr int kPullRounds = 16;  // per-lane steps (kUnroll entries each) before the wave helps
 constexpr int kEvPerLevel = 5;
+constexpr int kPullTileDense = 64;  // bitmap words per wave tile of the dense pull
+constexpr int kPullTileBU = 4;      // ... and of the bottom-up pull (many more candidates)
+constexpr int32_t kDirTD = CSBFS_DIR_TOP_DOWN, kDirBU = CSBFS_DIR_BOTTOM_UP, kDirDense = CSBFS_DIR_DENSE;
 
 struct BigItem {
     int32_t block;
@@ -64,6 +74,7 @@ struct ExpandArgs {
     int32_t P;
     unsigned long long *edges;
     int32_t *status;
+    const int32_t *dir;        // device direction of this level; the kernels run if top-down
 };
 
 
@@ -202,6 +213,7 @@ __device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int6
 // sources are spread evenly over the lanes, kUnroll edges per lane per step.
 template <bool kDense>
 __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
+    if (*a.dir == kDirBU) return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -219,6 +231,7 @@ __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
 // processor, strided over the grid.
 template <bool kDense>
 __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
+    if (*a.dir == kDirBU) return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -261,6 +274,7 @@ __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
 struct PullArgs {
     const uint64_t *S;
     const uint64_t *pi;
+    const uint64_t *live;  // vertices with at least one adjacency entry
     const uint64_t *view;
     const int32_t *row_ptr;
     const int64_t *col_base;
@@ -270,28 +284,45 @@ struct PullArgs {
     int64_t R;
     int64_t W;
     int32_t P;
+    int32_t tile_words;  // bitmap words per wave tile (<= 64)
     int32_t *status;
+    const int32_t *dir;
+    unsigned long long *edges;   // bottom-up: entries read
+    unsigned long long *pulled;  // bottom-up: candidates examined
 };
 
-// Dense evaluation, second half: parent[v] for every vertex v discovered in
-// this level (S & ~pi). A wavefront takes 64 words at a time and ranks their
-// new vertices, 64 at a time (lane = v). Each lane walks the rows of v from
-// block j = P-1 down to 0, each row in decreasing id order, kUnroll entries
-// per step, and stops at the first source found in its views. Lanes still
-// searching after kPullRounds steps are finished by the whole wave, 64
-// entries per step.
+// Pull: a vertex v of R_i walks its rows from block j = P-1 down to 0, each
+// row in decreasing id order, and stops at the first neighbour set in view
+// (i, j): the highest-labelled frontier neighbour.
+//   dense (second half of the dense evaluation): the candidates are the
+//       vertices discovered in this level (S & ~pi); each has a frontier
+//       neighbour.
+//   bottom-up: the candidates are the unvisited vertices with at least one
+//       adjacency entry (~pi & live); one that finds no frontier neighbour
+//       stays unvisited.
+// A wavefront takes tile_words bitmap words at a time and ranks their
+// candidates, 64 at a time (lane = v). Each lane reads kUnroll entries per
+// step; lanes still searching after kPullRounds steps are finished by the
+// whole wave, 64 entries per step.
+template <bool kBottomUp>
 __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
+    if (kBottomUp && *a.dir != kDirBU) return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t ntiles = (a.words + 63) >> 6;
+    const int64_t tw_n = a.tile_words;
+    const int64_t ntiles = (a.words + tw_n - 1) / tw_n;
+    unsigned long long read = 0, examined = 0;
     for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
-        const int64_t wq = (tile << 6) + lane;
-        const uint64_t t = wq < a.words ? (a.S[wq] & ~a.pi[wq]) : 0;
+        const int64_t wq = tile * tw_n + lane;
+        uint64_t t = 0;
+        if (lane < tw_n && wq < a.words)
+            t = kBottomUp ? (a.live[wq] & ~a.pi[wq]) : (a.S[wq] & ~a.pi[wq]);
         const int cnt = __popcll(t);
         const int incl_b = wave_incl_scan_i32(cnt);
         const int tot_b = __shfl(incl_b, 63, 64);
         const int excl_b = incl_b - cnt;
+        examined += (unsigned long long)tot_b;
         for (int base = 0; base < tot_b; base += 64) {
             const int r = base + lane;
             const int L = owner_lane(excl_b, r < tot_b ? r : tot_b - 1);
@@ -303,7 +334,7 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
             int32_t j = a.P - 1, e = 0, re = 0;
             int32_t found = -1;
             if (mine) {
-                const int64_t qq = (tile << 6) + L;
+                const int64_t qq = tile * tw_n + L;
                 i = (int32_t)(qq / a.W);
                 vl = ((qq - (int64_t)i * a.W) << 6) + select_bit(tw, rr);
                 const int32_t *rp = a.row_ptr + ((int64_t)j * a.P + i) * (a.R + 1) + vl;
@@ -321,21 +352,32 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
                         re = rp[1];
                     }
                     if (e == re) {
-                        busy = false;  // no frontier neighbour: impossible for a seen vertex
+                        busy = false;  // rows exhausted: no frontier neighbour
                     } else {
+                        // every lane reads kUnroll entries, positions past the row end
+                        // clamped to its last entry (nk >= 1 here) and masked out of
+                        // the hits: the loads need no per-entry branch
                         const int32_t nk = re - e < kUnroll ? re - e : kUnroll;
                         const uint32_t *cp = a.col + a.col_base[(int64_t)j * a.P + i] + e;
+                        const uint64_t *vj = vw + (int64_t)j * a.W;
                         uint32_t c[kUnroll];
                         uint64_t x[kUnroll];
 #pragma unroll
-                        for (int k = 0; k < kUnroll; ++k) c[k] = k < nk ? cp[k] : 0u;
+                        for (int k = 0; k < kUnroll; ++k) c[k] = cp[k < nk ? k : nk - 1];
 #pragma unroll
-                        for (int k = 0; k < kUnroll; ++k)
-                            x[k] = k < nk ? vw[(int64_t)j * a.W + (c[k] >> 6)] : 0ull;
+                        for (int k = 0; k < kUnroll; ++k) x[k] = vj[c[k] >> 6];
+                        uint32_t hm = 0;
 #pragma unroll
-                        for (int k = kUnroll - 1; k >= 0; --k)
-                            if ((x[k] >> (c[k] & 63)) & 1) found = (int32_t)(j * a.R + c[k]);
-                        if (found >= 0) busy = false;
+                        for (int k = 0; k < kUnroll; ++k) hm |= (uint32_t)((x[k] >> (c[k] & 63)) & 1) << k;
+                        hm &= (1u << nk) - 1u;
+                        const int hit = hm ? __builtin_ctz(hm) : -1;
+                        if (hit >= 0) {
+                            found = (int32_t)(j * a.R + c[hit]);
+                            busy = false;
+                            read += (unsigned long long)(hit + 1);
+                        } else {
+                            read += (unsigned long long)nk;
+                        }
                         e += nk;
                     }
                 }
@@ -372,8 +414,10 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
                     if (hits) {
                         const int first = __ffsll((unsigned long long)hits) - 1;
                         got = (int32_t)(jj * a.R + __shfl(ul, first, 64));
+                        if (lane == 0) read += (unsigned long long)(first + 1);
                         break;
                     }
+                    if (lane == 0) read += (unsigned long long)min(64, rr2 - ee);
                     ee += 64;
                 }
                 if (lane == Ls) found = got;
@@ -381,9 +425,16 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
             if (mine) {
                 if (found >= 0)
                     a.parent[(int64_t)i * a.R + vl] = found;
-                else
-                    *a.status = 3;
+                else if (!kBottomUp)
+                    *a.status = 3;  // a vertex seen in this level has a frontier neighbour
             }
+        }
+    }
+    if (kBottomUp) {
+        for (int d = 32; d > 0; d >>= 1) read += __shfl_xor(read, d, 64);
+        if (lane == 0) {
+            if (read) atomicAdd(a.edges, read);
+            if (examined) atomicAdd(a.pulled, examined);
         }
     }
 }
@@ -400,8 +451,9 @@ struct UpdateArgs {
     int64_t W;      // words per processor
     int32_t P;
     unsigned long long *rank_count;  // [P]
-    unsigned long long *total;       // [1]: frontier size
+    unsigned long long *total;       // [2]: frontier size, its adjacency entries
     uint32_t *ctrs;                  // [P]: chunk-queue counts, reset for the next level
+    const int32_t *deg;              // [n]: adjacency entries per vertex
 };
 
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
@@ -445,14 +497,72 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
         atomicAdd(&a.rank_count[q / a.W], (unsigned long long)c);
         atomicAdd(&a.total[0], (unsigned long long)c);
     }
-    // level of every new vertex, one coalesced row of 64 per non-zero word
+    // level of every new vertex, one coalesced row of 64 per non-zero word;
+    // the adjacency entries of the new frontier feed the direction choice
     uint64_t nz = __ballot(t != 0);
+    unsigned long long dsum = 0;
     while (nz) {
         const int src = __ffsll((unsigned long long)nz) - 1;
         nz &= nz - 1;
         const uint64_t tw = __shfl(t, src, 64);
-        if ((tw >> lane) & 1) a.level[((q0 + src) << 6) + lane] = a.next_level;
+        if ((tw >> lane) & 1) {
+            const int64_t v = ((q0 + src) << 6) + lane;
+            a.level[v] = a.next_level;
+            dsum += (unsigned long long)a.deg[v];
+        }
     }
+    for (int d = 32; d > 0; d >>= 1) dsum += __shfl_xor(dsum, d, 64);
+    if (lane == 0 && dsum) atomicAdd(&a.total[1], dsum);
+}
+
+// Direction state carried from level to level on the device.
+struct DirState {
+    int32_t cur;              // direction of the level expanded next
+    int32_t pad;
+    unsigned long long vdeg;  // adjacency entries of the visited vertices
+    unsigned long long prev;  // size of the frontier before the newest one
+};
+
+struct DirArgs {
+    DirState *st;
+    const unsigned long long *ctl;  // [2]: |f^{k+1}|, its adjacency entries
+    int32_t *rec;                   // direction recorded for level k + 1
+    int64_t n;
+    int64_t nnz;
+    float alpha;
+    float beta;
+    int32_t force;  // < 0: choose by the rule; else this direction at every level
+};
+
+// Beamer's rule (Sec. VIII names direction optimization as the next step):
+// m_f = entries of the new frontier, m_u = entries of unvisited vertices.
+// Top-down turns bottom-up when m_f * alpha > m_u; bottom-up turns top-down
+// when the frontier is below n / beta and shrinking.
+__global__ void direction_kernel(DirArgs a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const unsigned long long nf = a.ctl[0], mf = a.ctl[1];
+    DirState s = *a.st;
+    s.vdeg += mf;
+    const double mu = (double)a.nnz - (double)s.vdeg;
+    int32_t next = s.cur;
+    if (a.force >= 0) {
+        next = a.force;
+    } else if (s.cur == kDirTD) {
+        if (a.alpha > 0.f && (double)mf * (double)a.alpha > mu) next = kDirBU;
+    } else if ((double)nf * (double)a.beta < (double)a.n && nf < s.prev) {
+        next = kDirTD;
+    }
+    s.prev = nf;
+    s.cur = next;
+    *a.st = s;
+    *a.rec = next;
+}
+
+// Vertices with at least one adjacency entry, one bit each.
+__global__ void live_kernel(const int32_t *deg, int64_t n, uint64_t *live) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const uint64_t b = __ballot(v < n && deg[v] > 0);
+    if ((threadIdx.x & 63) == 0 && v < n) live[v >> 6] = b;
 }
 
 struct SeedArgs {
@@ -484,8 +594,16 @@ __global__ void seed_fill_kernel(SeedArgs a) {
 
 // f(s) <- s: the source is known to every processor without a message.
 __global__ void seed_root_kernel(SeedArgs a, int64_t root, int64_t R, int64_t W, int32_t P,
-                                 unsigned long long *ctl0, unsigned long long *rank0) {
+                                 unsigned long long *ctl0, unsigned long long *rank0,
+                                 const int32_t *deg, DirState *ds, int32_t *rec0, int32_t dir0) {
     const int64_t own = root / R, rl = root - own * R;
+    DirState s;
+    s.cur = dir0;
+    s.pad = 0;
+    s.vdeg = (unsigned long long)deg[root];
+    s.prev = 1;
+    *ds = s;
+    *rec0 = dir0;
     a.level[root] = 0;
     a.parent[root] = (int32_t)root;
     a.pi[root >> 6] |= 1ull << (root & 63);
@@ -507,9 +625,11 @@ struct LevelCounters {
     unsigned long long *ctl;     // [L+1][2]: |f^k|, sum of degrees over f^k
     unsigned long long *rank;    // [L+1][P]
     unsigned long long *edges;   // [L+1]
+    unsigned long long *pulled;  // [L+1]
     unsigned long long *sbits;   // [L+1][S]
     unsigned long long *uwords;  // [L+1][P]
     int64_t *words;              // [L+1][S]
+    int32_t *dir;                // [L+1]: direction used to expand f^k
 };
 
 struct csbfs_engine {
@@ -533,9 +653,10 @@ struct csbfs_engine {
     hipEvent_t count_ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> events;
     int32_t last_levels = 0;
-    // The dense evaluation is used only when asked for: measured on R-MAT
-    // graphs, the atomicMax push is faster at every level.
-    bool dense_default = false;
+    uint64_t *live = nullptr;    // [n / 64]: vertices with adjacency entries
+    DirState *dstate = nullptr;
+    // Beamer's parameters of the per-level direction choice
+    float alpha = 4.0f, beta = 64.0f;
     std::vector<void *> allocs;
 };
 
@@ -570,10 +691,11 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     if (max_levels < 1 || max_levels > 65536)
         return fail(CSBFS_EINVAL, "csbfs_engine_create: max_levels outside [1, 65536]");
     if (flags & ~(CSBFS_FLAG_TIMING | CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE |
-                  CSBFS_FLAG_SPARSE_ONLY | CSBFS_FLAG_DENSE_ONLY))
+                  CSBFS_FLAG_SPARSE_ONLY | CSBFS_FLAG_DENSE_ONLY | CSBFS_FLAG_BOTTOM_UP_ONLY))
         return fail(CSBFS_EINVAL, "csbfs_engine_create: unknown flag");
-    if ((flags & CSBFS_FLAG_SPARSE_ONLY) && (flags & CSBFS_FLAG_DENSE_ONLY))
-        return fail(CSBFS_EINVAL, "csbfs_engine_create: SPARSE_ONLY and DENSE_ONLY exclude each other");
+    const uint32_t modes = flags & (CSBFS_FLAG_SPARSE_ONLY | CSBFS_FLAG_DENSE_ONLY | CSBFS_FLAG_BOTTOM_UP_ONLY);
+    if (modes & (modes - 1))
+        return fail(CSBFS_EINVAL, "csbfs_engine_create: SPARSE_ONLY, DENSE_ONLY and BOTTOM_UP_ONLY exclude each other");
     int rc = graph_device_check(g);
     if (rc) return rc;
     csbfs_engine *e = new csbfs_engine();
@@ -613,9 +735,11 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     ALLOC(e->ctrs, sizeof(uint32_t) * P);
     ALLOC(e->qoff, sizeof(int64_t) * (P + 1));
     ALLOC(e->status, sizeof(int32_t));
+    ALLOC(e->live, sizeof(uint64_t) * words);
+    ALLOC(e->dstate, sizeof(DirState));
     const int64_t slots = (int64_t)max_levels + 1;
-    const size_t cnt_bytes = sizeof(unsigned long long) * slots * (2 + P + 1 + e->S + P) +
-                             sizeof(int64_t) * slots * e->S;
+    const size_t cnt_bytes = sizeof(unsigned long long) * slots * (2 + P + 1 + 1 + e->S + P) +
+                             sizeof(int64_t) * slots * e->S + sizeof(int32_t) * slots;
     ALLOC(e->counters_mem, cnt_bytes);
 #undef ALLOC
     e->counters_bytes = cnt_bytes;
@@ -626,15 +750,25 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     c += slots * P;
     e->lc.edges = c;
     c += slots;
+    e->lc.pulled = c;
+    c += slots;
     e->lc.sbits = c;
     c += slots * e->S;
     e->lc.uwords = c;
     c += slots * P;
     e->lc.words = (int64_t *)c;
+    e->lc.dir = (int32_t *)(e->lc.words + slots * e->S);
     hipError_t herr = hipMemcpy(e->qoff, qoff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice);
     if (herr != hipSuccess) {
         engine_release(e);
         return hip_fail(herr, "hipMemcpy(qoff)", __FILE__, __LINE__);
+    }
+    hipLaunchKernelGGL(live_kernel, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, 0, g->deg, n, e->live);
+    herr = hipGetLastError();
+    if (herr == hipSuccess) herr = hipDeviceSynchronize();
+    if (herr != hipSuccess) {
+        engine_release(e);
+        return hip_fail(herr, "live_kernel", __FILE__, __LINE__);
     }
     herr = hipHostMalloc((void **)&e->host_ctl, 4 * sizeof(unsigned long long));
     if (herr != hipSuccess) {
@@ -665,6 +799,15 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     return CSBFS_OK;
 }
 
+extern "C" int csbfs_engine_set_direction(csbfs_engine *e, float alpha, float beta) {
+    if (!e) return fail(CSBFS_EINVAL, "csbfs_engine_set_direction: engine is NULL");
+    if (!(beta > 0.f) || alpha != alpha)
+        return fail(CSBFS_EINVAL, "csbfs_engine_set_direction: beta must be > 0 and alpha a number");
+    e->alpha = alpha;
+    e->beta = beta;
+    return CSBFS_OK;
+}
+
 extern "C" int csbfs_engine_free(csbfs_engine *e) {
     if (!e) return CSBFS_OK;
     engine_release(e);
@@ -680,6 +823,7 @@ int reset_overflow_slot(csbfs_engine *e, hipStream_t st) {
     CSBFS_HIP(hipMemsetAsync(e->lc.ctl + 2 * L, 0, 2 * sizeof(unsigned long long), st));
     CSBFS_HIP(hipMemsetAsync(e->lc.rank + L * P, 0, sizeof(unsigned long long) * P, st));
     CSBFS_HIP(hipMemsetAsync(e->lc.edges + L, 0, sizeof(unsigned long long), st));
+    CSBFS_HIP(hipMemsetAsync(e->lc.pulled + L, 0, sizeof(unsigned long long), st));
     CSBFS_HIP(hipMemsetAsync(e->lc.sbits + L * S, 0, sizeof(unsigned long long) * S, st));
     CSBFS_HIP(hipMemsetAsync(e->lc.uwords + L * P, 0, sizeof(unsigned long long) * P, st));
     return CSBFS_OK;
@@ -702,6 +846,15 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     const bool timing = (e->flags & CSBFS_FLAG_TIMING) != 0;
     const bool keep = (e->flags & CSBFS_FLAG_KEEP_STREAMS) != 0;
 
+    // evaluation of the product: dense, or top-down / bottom-up per level
+    // (forced by a flag, or chosen on the device after every update)
+    const bool dense = (e->flags & CSBFS_FLAG_DENSE_ONLY) != 0;
+    const bool td_only = (e->flags & CSBFS_FLAG_SPARSE_ONLY) != 0 || (!dense && !(e->alpha > 0.f) &&
+                                                                      !(e->flags & CSBFS_FLAG_BOTTOM_UP_ONLY));
+    const bool bu_only = (e->flags & CSBFS_FLAG_BOTTOM_UP_ONLY) != 0;
+    const int32_t force = dense ? kDirDense : td_only ? kDirTD : bu_only ? kDirBU : -1;
+    const int32_t dir0 = dense ? kDirDense : bu_only ? kDirBU : kDirTD;
+
     // a0: seed
     CSBFS_HIP(hipMemsetAsync(e->counters_mem, 0, e->counters_bytes, st));
     CSBFS_HIP(hipMemsetAsync(e->status, 0, sizeof(int32_t), st));
@@ -711,7 +864,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     hipLaunchKernelGGL(seed_fill_kernel, dim3(grid_for(fill_items, 256, 8192)), dim3(256), 0, st, sa);
     CSBFS_HIP(hipGetLastError());
     hipLaunchKernelGGL(seed_root_kernel, dim3(1), dim3(1), 0, st, sa, root, R, W, (int32_t)P,
-                       e->lc.ctl, e->lc.rank);
+                       e->lc.ctl, e->lc.rank, (const int32_t *)g->deg, e->dstate, e->lc.dir, dir0);
     CSBFS_HIP(hipGetLastError());
 
     ExpandArgs ea{};
@@ -730,12 +883,37 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     ea.W = W;
     ea.P = (int32_t)P;
     ea.status = e->status;
-    PullArgs pa{e->seen, e->pi, e->view, g->row_ptr, g->col_base, g->col, parent, words, R, W,
-                (int32_t)P, e->status};
+    ea.dir = &e->dstate->cur;
+    PullArgs pa{};
+    pa.S = e->seen;
+    pa.pi = e->pi;
+    pa.live = e->live;
+    pa.view = e->view;
+    pa.row_ptr = g->row_ptr;
+    pa.col_base = g->col_base;
+    pa.col = g->col;
+    pa.parent = parent;
+    pa.words = words;
+    pa.R = R;
+    pa.W = W;
+    pa.P = (int32_t)P;
+    pa.status = e->status;
+    pa.dir = &e->dstate->cur;
+    PullArgs pb = pa;
+    pa.tile_words = kPullTileDense;
+    pb.tile_words = kPullTileBU;
     // one resident wave per SIMD slot of every CU, a multiple of the XCD count
     const unsigned exp_grid = 2048, big_grid = 2048;
-    const unsigned pull_grid = grid_for((words + 63) / 64, kPullThreads / 64, 16384);
+    const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
+    const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 16384);
     const unsigned upd_grid = grid_for(words, kUpdThreads, 1u << 30);
+    DirArgs da{};
+    da.st = e->dstate;
+    da.n = n;
+    da.nnz = g->nnz;
+    da.alpha = e->alpha;
+    da.beta = e->beta;
+    da.force = force;
 
     WahBatch wb{};
     wb.bits_base = e->f;
@@ -751,10 +929,6 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     wb.nchunk = e->nchunk;
     wb.dst_base = e->view;
     wb.status = e->status;
-
-    bool dense = e->dense_default;
-    if (e->flags & CSBFS_FLAG_SPARSE_ONLY) dense = false;
-    if (e->flags & CSBFS_FLAG_DENSE_ONLY) dense = true;
 
     // Iteration j: the messages carrying f^j (j >= 1: sieve + compress, then
     // decode into the views), the expansion of f^j, the update producing
@@ -793,19 +967,33 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
             CSBFS_HIP(hipGetLastError());
             hipLaunchKernelGGL(expand_big_kernel<true>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
             CSBFS_HIP(hipGetLastError());
-            hipLaunchKernelGGL(pull_kernel, dim3(pull_grid), dim3(kPullThreads), 0, st, pa);
+            hipLaunchKernelGGL(pull_kernel<false>, dim3(pull_grid), dim3(kPullThreads), 0, st, pa);
             CSBFS_HIP(hipGetLastError());
         } else {
-            hipLaunchKernelGGL(expand_kernel<false>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
-            CSBFS_HIP(hipGetLastError());
-            hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
-            CSBFS_HIP(hipGetLastError());
+            // the kernels of the direction not chosen for this level return at once
+            if (!bu_only) {
+                hipLaunchKernelGGL(expand_kernel<false>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
+                CSBFS_HIP(hipGetLastError());
+                hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
+                CSBFS_HIP(hipGetLastError());
+            }
+            if (!td_only) {
+                pb.edges = e->lc.edges + sj;
+                pb.pulled = e->lc.pulled + sj;
+                hipLaunchKernelGGL(pull_kernel<true>, dim3(bu_grid), dim3(kPullThreads), 0, st, pb);
+                CSBFS_HIP(hipGetLastError());
+            }
         }
         if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
-        // a2: mask, visit, f^{j+1}; a3: reduction of |f^{j+1}|
+        // a2: mask, visit, f^{j+1}; a3: reduction of |f^{j+1}| and of its
+        // adjacency entries; then the direction of level j + 1
         UpdateArgs ua{parent, e->seen, e->pi, e->f, e->view, level, (int32_t)(j + 1), words, W,
-                      (int32_t)P, e->lc.rank + sn * P, e->lc.ctl + 2 * sn, e->ctrs};
+                      (int32_t)P, e->lc.rank + sn * P, e->lc.ctl + 2 * sn, e->ctrs, g->deg};
         hipLaunchKernelGGL(update_kernel, dim3(upd_grid), dim3(kUpdThreads), 0, st, ua);
+        CSBFS_HIP(hipGetLastError());
+        da.ctl = e->lc.ctl + 2 * sn;
+        da.rec = e->lc.dir + sn;
+        hipLaunchKernelGGL(direction_kernel, dim3(1), dim3(64), 0, st, da);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
         const int hs = (int)((j + 1) & 1);
@@ -841,11 +1029,17 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     CSBFS_HIP(hipMemcpyAsync(&hstatus, e->status, sizeof(hstatus), hipMemcpyDeviceToHost, st));
     const int64_t have = nl < e->L ? nl : e->L;
     const int64_t want = stats_cap < have ? stats_cap : have;
-    std::vector<unsigned long long> ctl, ed, sb, uw;
+    std::vector<unsigned long long> ctl, ed, sb, uw, pl;
     std::vector<int64_t> wd;
+    std::vector<int32_t> dr;
     if (want > 0) {
         ctl.resize(2 * want);
         ed.resize(want);
+        pl.resize(want);
+        dr.resize(want);
+        CSBFS_HIP(hipMemcpyAsync(pl.data(), e->lc.pulled, sizeof(unsigned long long) * want,
+                                 hipMemcpyDeviceToHost, st));
+        CSBFS_HIP(hipMemcpyAsync(dr.data(), e->lc.dir, sizeof(int32_t) * want, hipMemcpyDeviceToHost, st));
         sb.resize(want * S);
         uw.resize(want * P);
         wd.resize(want * S);
@@ -870,6 +1064,8 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         s = csbfs_level_stats{};
         s.frontier = (int64_t)ctl[2 * lv];
         s.edges = (int64_t)ed[lv];
+        s.pulled = (int64_t)pl[lv];
+        s.direction = dr[lv];
         s.view_bits = P;  // the source is set in every view at level 0
         if (lv > 0) {
             int64_t sieved = 0, sent = 0, self = 0, uws = 0, maxr = 0;

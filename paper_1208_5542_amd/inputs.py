@@ -136,10 +136,12 @@ class Workload:
                           graph_seed(self.scale) + 2)
 
 
-# The three single-root workloads: a small parity case on one partition, a
-# 4 x 4 block grid at scale 22 and an 8 x 8 block grid at scale 26.
+# The single-root workloads: a small parity case on one partition, a 4 x 4
+# block grid at scale 22 and an 8 x 8 block grid at scale 26; and the batched
+# one: 64 roots searched together at scale 24 on a 4 x 4 grid.
 WORKLOADS = {
     "rmat10_p1": Workload("rmat10_p1", 10, 1, 16),
     "rmat22_p4": Workload("rmat22_p4", 22, 4, 64),
     "rmat26_p8": Workload("rmat26_p8", 26, 8, 64),
+    "rmat24_p4": Workload("rmat24_p4", 24, 4, 64),
 }

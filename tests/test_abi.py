@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_version_and_status_strings(lib):
     from paper_1208_5542_amd import csbfs
-    assert csbfs.version() == 10000
+    assert csbfs.version() == 10100
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert csbfs.strerror(code) != "unknown status"
     assert csbfs.strerror(-99) == "unknown status"
@@ -62,6 +62,11 @@ def test_host_side_argument_checks(lib):
     assert lib.csbfs_graph_build(None, None, 0, 1024, 1, None, None) == -1
     # engine and search on null handles
     assert lib.csbfs_engine_create(None, 64, 0, ctypes.byref(h)) == -1
+    assert lib.csbfs_engine_set_direction(None, 4.0, 64.0) == -1
+    assert lib.csbfs_batch_engine_create(None, 64, 64, 0, ctypes.byref(h)) == -1
+    assert lib.csbfs_batch_bfs(None, None, 0, None, None, 0, None, None) == -1
+    assert lib.csbfs_batch_stream_words(None, None, 0) == -1
+    assert lib.csbfs_batch_engine_free(None) == 0
     assert lib.csbfs_bfs(None, 0, None, None, None, 0, None, None) == -1
     assert lib.csbfs_engine_stream_words(None, None, 0) == -1
     assert lib.csbfs_engine_copy_stream(None, 0, 0, 0, None, 0, None, None) == -1
@@ -83,4 +88,15 @@ def test_package_import_does_not_need_a_gpu():
     import importlib
     import paper_1208_5542_amd.csbfs as m
     importlib.reload(m)
-    assert m.FLAG_TIMING == 1 and m.FLAG_DENSE_ONLY == 16
+    assert m.FLAG_TIMING == 1 and m.FLAG_DENSE_ONLY == 16 and m.FLAG_BOTTOM_UP_ONLY == 32
+
+
+def test_level_stats_layout_matches_header():
+    """The binding's struct has the header's field order and size."""
+    from paper_1208_5542_amd import csbfs
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct csbfs_level_stats {"):text.index("} csbfs_level_stats;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b(?:int64_t|int32_t|float)\s+(\w+);", body)
+    assert names == [f[0] for f in csbfs.LevelStats._fields_]
+    assert ctypes.sizeof(csbfs.LevelStats) == 11 * 8 + 4 * 4 + 2 * 4

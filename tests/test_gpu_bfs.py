@@ -96,7 +96,7 @@ def _check_search(eng, g, n, p, src, dst, root, adj, V, keep=True, max_levels=64
     return r
 
 
-MODES = {"auto": 0, "sparse": 8, "dense": 16}
+MODES = {"auto": 0, "sparse": 8, "dense": 16, "bottom_up": 32}
 
 
 @pytest.mark.parametrize("mode", list(MODES))
@@ -134,6 +134,50 @@ def test_sparse_graph_many_levels():
         log(f"search long path mode={mode}")
         r = _check_search(eng, g, n, p, src, dst, int(perm[0]), adj, V, keep=False, max_levels=4096)
         assert r.n_levels > 50
+
+
+def test_direction_choice_and_parameters():
+    """Direction-optimizing levels: the default rule turns bottom-up on an
+    R-MAT graph, the parameters force either direction, and every choice
+    gives the oracle's levels, parents and streams."""
+    from paper_1208_5542_amd import csbfs
+    n, src, dst = _graph(14)
+    p = 4
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst).reshape(-1)
+    root = int(inputs.pick_roots(n, src, dst, 1, 21)[0])
+    eng = csbfs.Engine(g, flags=csbfs.FLAG_KEEP_STREAMS)
+    log("direction: default rule")
+    r = _check_search(eng, g, n, p, src, dst, root, adj, V)
+    dirs = [s["direction"] for s in r.stats]
+    assert dirs[0] == csbfs.DIR_TOP_DOWN and csbfs.DIR_BOTTOM_UP in dirs, dirs
+    for s in r.stats:
+        if s["direction"] == csbfs.DIR_BOTTOM_UP:
+            assert s["pulled"] > 0 and s["edges"] > 0
+        else:
+            assert s["pulled"] == 0
+    log("direction: alpha = 0 (top-down only)")
+    eng.set_direction(0.0, 64.0)
+    r = _check_search(eng, g, n, p, src, dst, root, adj, V)
+    assert all(s["direction"] == csbfs.DIR_TOP_DOWN for s in r.stats)
+    log("direction: bottom-up from level 1 on")
+    eng.set_direction(1e9, 1e9)
+    r = _check_search(eng, g, n, p, src, dst, root, adj, V)
+    assert [s["direction"] for s in r.stats] == [0] + [1] * (r.n_levels - 1)
+    for bad in ((4.0, 0.0), (float("nan"), 1.0), (4.0, float("nan"))):
+        with pytest.raises(csbfs.CsbfsError) as ei:
+            eng.set_direction(*bad)
+        assert ei.value.status == csbfs.EINVAL
+    forced = csbfs.Engine(g, flags=csbfs.FLAG_BOTTOM_UP_ONLY)
+    r = forced.bfs(root)
+    assert all(s["direction"] == csbfs.DIR_BOTTOM_UP for s in r.stats)
+    dense = csbfs.Engine(g, flags=csbfs.FLAG_DENSE_ONLY)
+    r = dense.bfs(root)
+    assert all(s["direction"] == csbfs.DIR_DENSE for s in r.stats)
+    with pytest.raises(csbfs.CsbfsError) as ei:
+        csbfs.Engine(g, flags=csbfs.FLAG_BOTTOM_UP_ONLY | csbfs.FLAG_SPARSE_ONLY)
+    assert ei.value.status == csbfs.EINVAL
 
 
 def test_stats_truncated_beyond_max_levels():
