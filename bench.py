@@ -6,11 +6,17 @@ graph of scale 22 (edgefactor 16, initiator 0.57/0.19/0.19/0.05, ids permuted)
 on a 4 x 4 block grid (p = 4), roots drawn by the seeded root picker; K roots
 are timed after W warm-up roots. The graph is resident in HBM before timing.
 
+The timed searches run without instrumentation; the same roots are then
+searched again with per-kernel HIP events and level statistics for the byte
+counts, the time split and the roofline.
+
 Prints one JSON line: harmonic-mean GTEPS over the timed roots (TEPS = input
 tuples in the reached component / search time), compression ratios over all
 messages, the expansion step's roofline against HBM bandwidth (algorithmic
 bytes from the level statistics, time from HIP events recorded on the
-library's stream) and the CPU oracle timed on a bounded sample.
+library's stream), the batched comparison (64 roots in one batched search
+against the same roots one at a time, R-MAT scale 24) and the CPU oracle
+timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -41,8 +47,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2, help="untimed roots first")
     ap.add_argument("--workload", default="rmat22_p4", help="rmat10_p1 | rmat22_p4 | rmat26_p8")
     ap.add_argument("--no-sieve", action="store_true", help="Alg. 2 messages (no directory)")
-    ap.add_argument("--mode", default="auto", choices=["auto", "sparse", "dense"],
-                    help="evaluation of each level's product (results are identical)")
+    ap.add_argument("--mode", default="auto", choices=["auto", "sparse", "dense", "bottom_up"],
+                    help="evaluation of each level's product (results are identical): auto = "
+                         "top-down or bottom-up per level; sparse = top-down only")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-workload", default="rmat24_p4",
@@ -146,8 +153,8 @@ def batched_section(args):
     torch.cuda.synchronize()
     log(f"[bench] batched: graph {wl.name} built in {time.perf_counter() - t:.1f}s")
     B = len(roots)
-    beng = csbfs.BatchEngine(g, max_roots=64, max_levels=256, flags=csbfs.FLAG_TIMING)
-    seng = csbfs.Engine(g, max_levels=256, flags=csbfs.FLAG_TIMING)
+    beng = csbfs.BatchEngine(g, max_roots=64, max_levels=256)
+    seng = csbfs.Engine(g, max_levels=256)
     blevel = torch.empty((B, n), dtype=torch.int32, device="cuda")
     level = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -159,17 +166,18 @@ def batched_section(args):
     for _ in range(max(args.batch_reps, 1)):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        res = beng.bfs(roots, blevel)
+        res = beng.bfs(roots, blevel, with_stats=False)
         e1.record(stream)
         torch.cuda.synchronize()
         bms.append(e0.elapsed_time(e1))
-        bstats = res.stats
+    # statistics and per-kernel times from one more, instrumented, batch
+    bstats = csbfs.BatchEngine(g, max_roots=64, max_levels=256, flags=csbfs.FLAG_TIMING).bfs(roots, blevel).stats
     m = [g.traversed_tuples(blevel[b]) for b in range(B)]
     sms, match = [], True
     for b, r in enumerate(roots):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        seng.bfs(r, level, parent)
+        seng.bfs(r, level, parent, with_stats=False)
         e1.record(stream)
         torch.cuda.synchronize()
         sms.append(e0.elapsed_time(e1))
@@ -231,42 +239,51 @@ def main():
     torch.cuda.empty_cache()
     log(f"[bench] graph built p={p} nnz={g.info.nnz} max_block={g.info.max_block_nnz} "
         f"device={g.info.device_bytes / 2**30:.2f} GiB in {time.perf_counter() - t:.1f}s")
-    flags = csbfs.FLAG_TIMING | (csbfs.FLAG_NO_SIEVE if args.no_sieve else 0)
-    flags |= {"auto": 0, "sparse": csbfs.FLAG_SPARSE_ONLY, "dense": csbfs.FLAG_DENSE_ONLY}[args.mode]
+    flags = csbfs.FLAG_NO_SIEVE if args.no_sieve else 0
+    flags |= {"auto": 0, "sparse": csbfs.FLAG_SPARSE_ONLY, "dense": csbfs.FLAG_DENSE_ONLY,
+              "bottom_up": csbfs.FLAG_BOTTOM_UP_ONLY}[args.mode]
+    # the timed pass runs uninstrumented (no per-kernel events, no counter
+    # readback); a second pass over the same roots with per-kernel timing
+    # gives the byte counts, the time split and the roofline
     eng = csbfs.Engine(g, max_levels=256, flags=flags)
+    probe = csbfs.Engine(g, max_levels=256, flags=flags | csbfs.FLAG_TIMING)
     level = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
     for r in roots[: args.warmup]:
-        eng.bfs(int(r), level, parent)
+        eng.bfs(int(r), level, parent, with_stats=False)
+        probe.bfs(int(r), level, parent)
     torch.cuda.synchronize()
     log(f"[bench] warmup done ({args.warmup} roots)")
 
     stream = torch.cuda.current_stream()
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    per_root = []
+    m_of = []
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     for k, r in enumerate(roots[args.warmup:]):
         ev0[k].record(stream)
-        res = eng.bfs(int(r), level, parent)
+        eng.bfs(int(r), level, parent, with_stats=False)
         ev1[k].record(stream)
-        per_root.append((int(r), res.n_levels, res.stats))
-        m = g.traversed_tuples(level)  # outside the recorded events
-        per_root[-1] = per_root[-1] + (m,)
+        m_of.append(g.traversed_tuples(level))  # outside the recorded events
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     times = [ev0[k].elapsed_time(ev1[k]) / 1e3 for k in range(args.steps)]
     ms = [t * 1e3 for t in times]
-    teps = [pr[3] / t for pr, t in zip(per_root, times)]
+    teps = [m / t for m, t in zip(m_of, times)]
     hmean = len(teps) / sum(1.0 / x for x in teps)
     log(f"[bench] timed {args.steps} roots in {wall:.2f}s wall; hmean {hmean / 1e9:.3f} GTEPS")
+    per_root = []
+    for r, m in zip(roots[args.warmup:], m_of):
+        res = probe.bfs(int(r), level, parent)
+        per_root.append((int(r), res.n_levels, res.stats, m))
 
     # bytes and compression over every message of every timed root
     tot = {k: 0 for k in ("raw_bytes", "wah_unsieved_bytes", "wah_sieved_bytes", "self_bytes",
                           "sieved_bits", "unsieved_bits", "edges", "view_bits")}
     inv_ratio, nlev = 0.0, 0
     exp_bytes, exp_ms, exp_launches = 0, 0.0, 0
+    dir_count = {"top_down": 0, "bottom_up": 0}
     cat_ms = {"expand": 0.0, "update": 0.0, "compress": 0.0, "decode": 0.0}
     R = n // p
     for _, nl, stats, _m in per_root:
@@ -276,10 +293,17 @@ def main():
             if k > 0 and s["wah_sieved_bytes"] > 0:
                 inv_ratio += s["wah_sieved_bytes"] / s["raw_bytes"]
                 nlev += 1
-            # algorithmic bytes of expanding f^k: column ids of every scanned
-            # row, the row-offset pair of every view bit, one pass over the p
-            # views and one over the visited bits
-            exp_bytes += 4 * s["edges"] + 8 * s["view_bits"] + p * n // 8 + n // 8
+            # algorithmic bytes of expanding f^k. Top-down: column ids of every
+            # scanned row, the row-offset pair of every view bit, one pass over
+            # the p views and one over the visited bits. Bottom-up: column ids
+            # read, one row-offset pair per examined vertex, the p views, and
+            # the visited and live bits scanned for candidates.
+            if s["direction"] == csbfs.DIR_BOTTOM_UP:
+                exp_bytes += 4 * s["edges"] + 8 * s["pulled"] + p * n // 8 + 2 * n // 8
+                dir_count["bottom_up"] += 1
+            else:
+                exp_bytes += 4 * s["edges"] + 8 * s["view_bits"] + p * n // 8 + n // 8
+                dir_count["top_down"] += 1
             exp_ms += s["ms_expand"]
             exp_launches += 1
             cat_ms["expand"] += s["ms_expand"]
@@ -323,7 +347,9 @@ def main():
                   "wah_sieved": tot["wah_sieved_bytes"], "self": tot["self_bytes"],
                   "bits_before_sieve": tot["unsieved_bits"], "bits_after_sieve": tot["sieved_bits"]},
         "time_split_ms": {k: round(v / args.steps, 4) for k, v in cat_ms.items()},
-        "roofline": {"bound": "hbm", "kernel": "expand (expand_kernel + expand_big_kernel)",
+        "levels_by_direction": dir_count,
+        "roofline": {"bound": "hbm",
+                     "kernel": "expansion step (expand_kernel + expand_big_kernel, or pull_kernel<bottom-up>)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": traffic,
@@ -332,7 +358,7 @@ def main():
         "wall_s": round(wall, 3),
     }
     if not args.no_batched:
-        del eng, g, level, parent
+        del eng, probe, g, level, parent
         torch.cuda.empty_cache()
         out["batched"] = batched_section(args)
     if not args.no_cpu_baseline:

@@ -193,8 +193,8 @@ int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags
  * vertices: a top-down search turns bottom-up when m_f * alpha > m_u; a
  * bottom-up search turns top-down again when |f^{k+1}| * beta < n and the
  * frontier shrank. Level 0 is top-down. alpha <= 0 keeps every level
- * top-down. Takes effect at the next csbfs_bfs. Errors: EINVAL (NULL
- * engine, beta <= 0 or a NaN).
+ * top-down. Defaults: alpha = 8, beta = 24. Takes effect at the next
+ * csbfs_bfs. Errors: EINVAL (NULL engine, beta <= 0 or a NaN).
  */
 int csbfs_engine_set_direction(csbfs_engine *e, float alpha, float beta);
 

@@ -75,15 +75,6 @@ __device__ __forceinline__ void brelax(const BArgs &a, const int64_t (&v)[kBUnro
         if (add[k] & ~have[k]) atomicOr((unsigned long long *)&a.nx[v[k]], (unsigned long long)add[k]);
 }
 
-// Orders a wave's LDS stores before its later LDS loads by other lanes (and
-// the loads before the next stores): LDS operations of one wave complete in
-// order, so only the compiler must be kept from moving them.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // A wave's tile: kBTile consecutive words of every root plane. Loads and
 // stores of a tile move 4 roots x kBTile words (four 128-byte lines) per
 // instruction; LDS turns them around so that lane r holds root r's word.

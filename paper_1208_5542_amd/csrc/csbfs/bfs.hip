@@ -11,10 +11,10 @@
 //              top-down (sparse): every set bit u of view (i, j) is a source
 //                      whose row in block (i, j) is pushed to its targets v
 //                      in R_i; an unvisited v takes u by atomicMax into
-//                      parent[v];
-//              bottom-up: every unvisited v of R_i scans its rows, sorted by
-//                      decreasing id, block j = P-1 down to 0, and stops at
-//                      the first neighbour set in view (i, j): the maximum;
+//                      parent[v], and its first discoverer sets its S bit;
+//              bottom-up: every unvisited v of R_i reads its merged row
+//                      (global ids in decreasing order) and stops at the
+//                      first neighbour set in P_i's views: the maximum;
 //              dense:  a top-down push that only sets S bits (a bitmap small
 //                      enough to stay in L2), then every new v pulls its
 //                      parent as in bottom-up.
@@ -30,8 +30,9 @@
 //   exchange           stream slot (i, j) is P_j's receive buffer from P_i
 //   decode/merge       view (j, i) |= WAH^-1(stream i -> j)    (wah.hip)
 //
-// Processor i's pull reads the row of v in A_{i,j}; by the symmetry of A it
-// is the same array as the column of v in A_{j,i}, block (j, i)'s storage.
+// Processor i's pull reads the column of v in its block-row A_{i,*}; by the
+// symmetry of A that is the row of v in blocks (j, i), which the graph keeps
+// merged per vertex (the pull layout) next to the blocks.
 #include <vector>
 
 #include "device.hpp"
@@ -82,8 +83,8 @@ constexpr int kUnroll = 4;  // independent edges in flight per lane
 
 // Relax kUnroll (target v, source u) pairs; every load is issued before any
 // result is used, so their latencies overlap.
-//   sparse: an unvisited v takes u by atomicMax into parent[v] (the update
-//           finds the new vertices as the unvisited ones with a parent).
+//   sparse: an unvisited v takes u by atomicMax into parent[v]; the lane
+//           that finds it still without a parent also sets its seen bit.
 //   dense:  v is only marked seen.
 template <bool kDense>
 __device__ __forceinline__ void relax_batch(const ExpandArgs &a, const int64_t (&v)[kUnroll],
@@ -110,9 +111,15 @@ __device__ __forceinline__ void relax_batch(const ExpandArgs &a, const int64_t (
             old[k] = need ? __hip_atomic_load(&a.parent[v[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                           : INT32_MAX;
         }
+        // The first atomicMax on a vertex comes from a lane whose load still
+        // saw no parent: that lane also marks the vertex seen, so S & ~pi
+        // is exactly this level's new vertices.
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k)
+        for (int k = 0; k < kUnroll; ++k) {
             if (old[k] < u[k]) atomicMax(&a.parent[v[k]], u[k]);
+            if (old[k] < 0)
+                atomicOr((unsigned long long *)&a.S[v[k] >> 6], (unsigned long long)(1ull << (v[k] & 63)));
+        }
     }
 }
 
@@ -272,13 +279,12 @@ __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
 }
 
 struct PullArgs {
-    const uint64_t *S;
+    uint64_t *S;
     const uint64_t *pi;
     const uint64_t *live;  // vertices with at least one adjacency entry
     const uint64_t *view;
-    const int32_t *row_ptr;
-    const int64_t *col_base;
-    const uint32_t *col;
+    const int64_t *pull_off;   // merged rows (global ids, decreasing) of every vertex
+    const uint32_t *pull_col;
     int32_t *parent;
     int64_t words;  // n / 64
     int64_t R;
@@ -291,15 +297,18 @@ struct PullArgs {
     unsigned long long *pulled;  // bottom-up: candidates examined
 };
 
-// Pull: a vertex v of R_i walks its rows from block j = P-1 down to 0, each
-// row in decreasing id order, and stops at the first neighbour set in view
-// (i, j): the highest-labelled frontier neighbour.
+// Pull: a vertex v of R_i reads its merged row (the rows of v in blocks
+// (j, i), j = P-1 down to 0, as global ids in decreasing order) and stops at
+// the first entry set in its views: the highest-labelled frontier neighbour.
+// P_i's views (i, 0..P-1) are consecutive R-bit pieces, so together they are
+// one n-bit map indexed by the global id.
 //   dense (second half of the dense evaluation): the candidates are the
 //       vertices discovered in this level (S & ~pi); each has a frontier
 //       neighbour.
 //   bottom-up: the candidates are the unvisited vertices with at least one
 //       adjacency entry (~pi & live); one that finds no frontier neighbour
-//       stays unvisited.
+//       stays unvisited. The found ones are gathered per bitmap word in LDS
+//       and set in S by the wave that owns the word.
 // A wavefront takes tile_words bitmap words at a time and ranks their
 // candidates, 64 at a time (lane = v). Each lane reads kUnroll entries per
 // step; lanes still searching after kPullRounds steps are finished by the
@@ -307,12 +316,15 @@ struct PullArgs {
 template <bool kBottomUp>
 __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
     if (kBottomUp && *a.dir != kDirBU) return;
+    __shared__ unsigned long long found_bits[kPullThreads / 64][kPullTileBU];
     const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t tw_n = a.tile_words;
+    const int64_t tw_n = a.tile_words;  // <= kPullTileBU in bottom-up
     const int64_t ntiles = (a.words + tw_n - 1) / tw_n;
     unsigned long long read = 0, examined = 0;
+    if (kBottomUp && lane < kPullTileBU) found_bits[wid][lane] = 0;
     for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
         const int64_t wq = tile * tw_n + lane;
         uint64_t t = 0;
@@ -329,56 +341,44 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
             const uint64_t tw = __shfl(t, L, 64);
             const int rr = r - __shfl(excl_b, L, 64);
             const bool mine = r < tot_b;
-            int32_t i = 0;
-            int64_t vl = 0;
-            int32_t j = a.P - 1, e = 0, re = 0;
+            int64_t v = 0, e = 0, re = 0;
+            int bitpos = 0;
             int32_t found = -1;
             if (mine) {
-                const int64_t qq = tile * tw_n + L;
-                i = (int32_t)(qq / a.W);
-                vl = ((qq - (int64_t)i * a.W) << 6) + select_bit(tw, rr);
-                const int32_t *rp = a.row_ptr + ((int64_t)j * a.P + i) * (a.R + 1) + vl;
-                e = rp[0];
-                re = rp[1];
+                bitpos = select_bit(tw, rr);
+                v = ((tile * tw_n + L) << 6) + bitpos;
+                e = a.pull_off[v];
+                re = a.pull_off[v + 1];
             }
-            const uint64_t *vw = a.view + (int64_t)i * a.P * a.W;  // views (i, *)
-            bool busy = mine;
+            const int64_t i = v / a.R;
+            const uint64_t *vw = a.view + i * a.P * a.W;  // P_i's views as one n-bit map
+            bool busy = mine && e < re;
             for (int round = 0; round < kPullRounds; ++round) {
                 if (busy) {
-                    while (e == re && j > 0) {
-                        --j;
-                        const int32_t *rp = a.row_ptr + ((int64_t)j * a.P + i) * (a.R + 1) + vl;
-                        e = rp[0];
-                        re = rp[1];
-                    }
-                    if (e == re) {
-                        busy = false;  // rows exhausted: no frontier neighbour
+                    // every lane reads kUnroll entries, positions past the row end
+                    // clamped to its last entry and masked out of the hits: the
+                    // loads need no per-entry branch
+                    const int32_t nk = re - e < kUnroll ? (int32_t)(re - e) : kUnroll;
+                    const uint32_t *cp = a.pull_col + e;
+                    uint32_t c[kUnroll];
+                    uint64_t x[kUnroll];
+#pragma unroll
+                    for (int k = 0; k < kUnroll; ++k) c[k] = cp[k < nk ? k : nk - 1];
+#pragma unroll
+                    for (int k = 0; k < kUnroll; ++k) x[k] = vw[c[k] >> 6];
+                    uint32_t hm = 0;
+#pragma unroll
+                    for (int k = 0; k < kUnroll; ++k) hm |= (uint32_t)((x[k] >> (c[k] & 63)) & 1) << k;
+                    hm &= (1u << nk) - 1u;
+                    if (hm) {
+                        const int hit = __builtin_ctz(hm);
+                        found = (int32_t)c[hit];
+                        busy = false;
+                        read += (unsigned long long)(hit + 1);
                     } else {
-                        // every lane reads kUnroll entries, positions past the row end
-                        // clamped to its last entry (nk >= 1 here) and masked out of
-                        // the hits: the loads need no per-entry branch
-                        const int32_t nk = re - e < kUnroll ? re - e : kUnroll;
-                        const uint32_t *cp = a.col + a.col_base[(int64_t)j * a.P + i] + e;
-                        const uint64_t *vj = vw + (int64_t)j * a.W;
-                        uint32_t c[kUnroll];
-                        uint64_t x[kUnroll];
-#pragma unroll
-                        for (int k = 0; k < kUnroll; ++k) c[k] = cp[k < nk ? k : nk - 1];
-#pragma unroll
-                        for (int k = 0; k < kUnroll; ++k) x[k] = vj[c[k] >> 6];
-                        uint32_t hm = 0;
-#pragma unroll
-                        for (int k = 0; k < kUnroll; ++k) hm |= (uint32_t)((x[k] >> (c[k] & 63)) & 1) << k;
-                        hm &= (1u << nk) - 1u;
-                        const int hit = hm ? __builtin_ctz(hm) : -1;
-                        if (hit >= 0) {
-                            found = (int32_t)(j * a.R + c[hit]);
-                            busy = false;
-                            read += (unsigned long long)(hit + 1);
-                        } else {
-                            read += (unsigned long long)nk;
-                        }
+                        read += (unsigned long long)nk;
                         e += nk;
+                        if (e >= re) busy = false;  // row exhausted: no frontier neighbour
                     }
                 }
                 if (!__ballot(busy)) break;
@@ -387,47 +387,50 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
             while (slow) {
                 const int Ls = __ffsll((unsigned long long)slow) - 1;
                 slow &= slow - 1;
-                int32_t jj = __shfl(j, Ls, 64);
-                int32_t ee = __shfl(e, Ls, 64);
-                int32_t rr2 = __shfl(re, Ls, 64);
-                const int32_t ii = __shfl(i, Ls, 64);
-                const int64_t vll = shfl64(vl, Ls);
-                const uint64_t *vws = a.view + (int64_t)ii * a.P * a.W;
+                int64_t ee = shfl64(e, Ls);
+                const int64_t rr2 = shfl64(re, Ls);
+                const int64_t ii = shfl64(i, Ls);
+                const uint64_t *vws = a.view + ii * a.P * a.W;
                 int32_t got = -1;
-                for (;;) {
-                    if (ee >= rr2) {
-                        if (jj == 0) break;
-                        --jj;
-                        const int32_t *rp = a.row_ptr + ((int64_t)jj * a.P + ii) * (a.R + 1) + vll;
-                        ee = rp[0];
-                        rr2 = rp[1];
-                        continue;
-                    }
-                    const int32_t pos = ee + lane;
+                for (; ee < rr2; ee += 64) {
+                    const int64_t pos = ee + lane;
                     bool hit = false;
-                    uint32_t ul = 0;
+                    uint32_t u = 0;
                     if (pos < rr2) {
-                        ul = a.col[a.col_base[(int64_t)jj * a.P + ii] + pos];
-                        hit = (vws[(int64_t)jj * a.W + (ul >> 6)] >> (ul & 63)) & 1;
+                        u = a.pull_col[pos];
+                        hit = (vws[u >> 6] >> (u & 63)) & 1;
                     }
                     const uint64_t hits = __ballot(hit);
                     if (hits) {
                         const int first = __ffsll((unsigned long long)hits) - 1;
-                        got = (int32_t)(jj * a.R + __shfl(ul, first, 64));
+                        got = (int32_t)__shfl((int32_t)u, first, 64);
                         if (lane == 0) read += (unsigned long long)(first + 1);
                         break;
                     }
-                    if (lane == 0) read += (unsigned long long)min(64, rr2 - ee);
-                    ee += 64;
+                    if (lane == 0) read += (unsigned long long)(rr2 - ee < 64 ? rr2 - ee : 64);
                 }
                 if (lane == Ls) found = got;
             }
             if (mine) {
-                if (found >= 0)
-                    a.parent[(int64_t)i * a.R + vl] = found;
-                else if (!kBottomUp)
+                if (found >= 0) {
+                    a.parent[v] = found;
+                    if (kBottomUp) atomicOr(&found_bits[wid][L], 1ull << bitpos);
+                } else if (!kBottomUp) {
                     *a.status = 3;  // a vertex seen in this level has a frontier neighbour
+                }
             }
+        }
+        if (kBottomUp) {
+            // this wave owns the tile's words of S: merge the found vertices
+            wave_lds_sync();
+            if (lane < tw_n && wq < a.words) {
+                const unsigned long long fb = found_bits[wid][lane];
+                if (fb) {
+                    a.S[wq] |= fb;
+                    found_bits[wid][lane] = 0;
+                }
+            }
+            wave_lds_sync();
         }
     }
     if (kBottomUp) {
@@ -440,8 +443,7 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
 }
 
 struct UpdateArgs {
-    const int32_t *parent;
-    uint64_t *S;
+    const uint64_t *S;
     uint64_t *pi;
     uint64_t *f;
     uint64_t *view;
@@ -461,22 +463,11 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     uint64_t t = 0;
     if (q < a.words) {
-        const uint64_t p = a.pi[q];
-        if (~p) {
-            // the new vertices of this word: unvisited ones that got a parent
-            const int4 *pp = reinterpret_cast<const int4 *>(a.parent + (q << 6));
-#pragma unroll 4
-            for (int k = 0; k < 16; ++k) {
-                const int4 x = pp[k];
-                t |= (uint64_t)(x.x >= 0) << (4 * k) | (uint64_t)(x.y >= 0) << (4 * k + 1) |
-                     (uint64_t)(x.z >= 0) << (4 * k + 2) | (uint64_t)(x.w >= 0) << (4 * k + 3);
-            }
-            t &= ~p;
-        }
-        if (t) {
-            a.pi[q] = p | t;
-            a.S[q] = p | t;
-        }
+        // the new vertices of this word: seen in this level, not yet visited
+        // (S holds pi and every vertex the expansion discovered)
+        const uint64_t p = a.pi[q], sq = a.S[q];
+        t = sq & ~p;
+        if (t) a.pi[q] = sq;
         a.f[q] = t;
         // clear processor i's views (i, j) at the same offset for every j
         const int64_t i = q / a.W, ql = q - i * a.W;
@@ -655,8 +646,9 @@ struct csbfs_engine {
     int32_t last_levels = 0;
     uint64_t *live = nullptr;    // [n / 64]: vertices with adjacency entries
     DirState *dstate = nullptr;
-    // Beamer's parameters of the per-level direction choice
-    float alpha = 4.0f, beta = 64.0f;
+    // Beamer's parameters of the per-level direction choice, measured best
+    // on R-MAT graphs of scale 22 (4 x 4) and 26 (8 x 8)
+    float alpha = 8.0f, beta = 24.0f;
     std::vector<void *> allocs;
 };
 
@@ -889,9 +881,8 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     pa.pi = e->pi;
     pa.live = e->live;
     pa.view = e->view;
-    pa.row_ptr = g->row_ptr;
-    pa.col_base = g->col_base;
-    pa.col = g->col;
+    pa.pull_off = g->pull_off;
+    pa.pull_col = g->pull_col;
     pa.parent = parent;
     pa.words = words;
     pa.R = R;
@@ -987,7 +978,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
         // a2: mask, visit, f^{j+1}; a3: reduction of |f^{j+1}| and of its
         // adjacency entries; then the direction of level j + 1
-        UpdateArgs ua{parent, e->seen, e->pi, e->f, e->view, level, (int32_t)(j + 1), words, W,
+        UpdateArgs ua{e->seen, e->pi, e->f, e->view, level, (int32_t)(j + 1), words, W,
                       (int32_t)P, e->lc.rank + sn * P, e->lc.ctl + 2 * sn, e->ctrs, g->deg};
         hipLaunchKernelGGL(update_kernel, dim3(upd_grid), dim3(kUpdThreads), 0, st, ua);
         CSBFS_HIP(hipGetLastError());

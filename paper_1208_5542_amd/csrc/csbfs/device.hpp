@@ -78,6 +78,15 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
     return v;
 }
 
+// Orders a wave's LDS stores before its later LDS loads by other lanes (and
+// the loads before the next stores): LDS operations of one wave complete in
+// order, so only the compiler must be kept from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 inline unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;

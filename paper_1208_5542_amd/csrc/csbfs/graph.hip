@@ -208,6 +208,26 @@ __global__ void k_count_m(const int32_t *level, const int32_t *deg, int64_t n,
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(out, s);
 }
 
+// Merge the rows of v in blocks (j, i), j = P-1 down to 0, into one row of
+// global ids: each block row is already in decreasing order and block j
+// holds the ids of R_j, so the merged row is in decreasing order. One
+// thread per vertex (setup only).
+__global__ void k_pull_fill(const int32_t *row_ptr, const int64_t *col_base, const uint32_t *col,
+                            int64_t R, int32_t P, int64_t n, const int64_t *pull_off, uint32_t *pull_col) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = v / R, vl = v - i * R;
+        int64_t d = pull_off[v];
+        for (int32_t j = P - 1; j >= 0; --j) {
+            const int64_t b = (int64_t)j * P + i;
+            const int32_t *rp = row_ptr + b * (R + 1) + vl;
+            const uint32_t *src = col + col_base[b];
+            const uint32_t base = (uint32_t)(j * R);
+            for (int32_t e = rp[0]; e < rp[1]; ++e) pull_col[d++] = base + src[e];
+        }
+    }
+}
+
 unsigned grid_for(int64_t items, int64_t per_block, unsigned cap = 65536) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -263,7 +283,7 @@ extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t
     g->W = W;
     g->n_tuples = n_tuples;
 
-    DevBuf cnt, sums, nnzb, err, rp, cb, col, dir, deg, scratch;
+    DevBuf cnt, sums, nnzb, err, rp, cb, col, dir, deg, scratch, poff, pcol;
     const int64_t ntile = (R + kTile - 1) / kTile;
     CSBFS_HIP(hipMalloc(&cnt.p, sizeof(int32_t) * B * R));
     CSBFS_HIP(hipMalloc(&sums.p, sizeof(long long) * B * ntile));
@@ -345,6 +365,24 @@ extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t
     if (total > 0 && (chk[0] >= (unsigned long long)R || chk[1] != (unsigned long long)total))
         return fail(CSBFS_ECORRUPT, "csbfs_graph_build: internal consistency check of the block "
                                     "CSR failed (column id or degree total)");
+    // pull layout for the bottom-up evaluation
+    CSBFS_HIP(cnt.p ? hipFree(cnt.release()) : hipSuccess);
+    CSBFS_HIP(hipMalloc(&poff.p, sizeof(int64_t) * (n + 1)));
+    CSBFS_HIP(hipMalloc(&pcol.p, sizeof(uint32_t) * (total > 0 ? total : 1)));
+    {
+        const int rc = degree_offsets((const int32_t *)deg.p, n, (int64_t *)poff.p, st);
+        if (rc) return rc;
+    }
+    int64_t pull_total = -1;
+    CSBFS_HIP(hipMemcpyAsync(&pull_total, (const int64_t *)poff.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    if (pull_total != total)
+        return fail(CSBFS_ECORRUPT, "csbfs_graph_build: pull-row offsets disagree with the blocks");
+    hipLaunchKernelGGL(k_pull_fill, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, (const int32_t *)rp.p,
+                       (const int64_t *)cb.p, (const uint32_t *)col.p, R, p, n, (const int64_t *)poff.p,
+                       (uint32_t *)pcol.p);
+    CSBFS_HIP(hipGetLastError());
+    CSBFS_HIP(hipStreamSynchronize(st));
 
     g->row_ptr = (int32_t *)rp.release();
     g->col_base = (int64_t *)cb.release();
@@ -352,13 +390,16 @@ extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t
     g->col = (uint32_t *)col.release();
     g->dir = (uint64_t *)dir.release();
     g->deg = (int32_t *)deg.release();
+    g->pull_off = (int64_t *)poff.release();
+    g->pull_col = (uint32_t *)pcol.release();
     g->scratch = (unsigned long long *)scratch.release();
     g->nnz = total;
     g->max_block_nnz = maxb;
     g->big_items.assign(big_items.begin(), big_items.end());
     g->device_bytes = (int64_t)(sizeof(int32_t) * B * (R + 1) + sizeof(int64_t) * (B + 1) +
                                 sizeof(uint32_t) * total + sizeof(uint64_t) * B * W +
-                                sizeof(int32_t) * n + 8 * 64);
+                                sizeof(int32_t) * n + 8 * 64 + sizeof(int64_t) * (n + 1) +
+                                sizeof(uint32_t) * total);
     *out = g.release();
     return CSBFS_OK;
 }
@@ -371,6 +412,8 @@ extern "C" int csbfs_graph_free(csbfs_graph *g) {
     (void)hipFree(g->col);
     (void)hipFree(g->dir);
     (void)hipFree(g->deg);
+    (void)hipFree(g->pull_off);
+    (void)hipFree(g->pull_col);
     (void)hipFree(g->scratch);
     delete g;
     return CSBFS_OK;

@@ -34,6 +34,11 @@ struct csbfs_graph {
     uint32_t *col = nullptr;          // [nnz], local target ids
     uint64_t *dir = nullptr;          // [P*P][W], V_{i,j} = non-empty rows of block (i, j)
     int32_t *deg = nullptr;           // [n], adjacency entries of u over all blocks
+    // Pull layout: the rows of v in blocks (j, i), j = P-1 down to 0, merged
+    // into one row of global ids in decreasing order (processor i's view of
+    // column v of its block-row; by symmetry the same entries as the blocks)
+    int64_t *pull_off = nullptr;      // [n + 1]
+    uint32_t *pull_col = nullptr;     // [nnz]
     unsigned long long *scratch = nullptr;  // small reduction scratch
 };
 
@@ -42,4 +47,6 @@ int graph_device_check(const csbfs_graph *g);
 // Sort every block row (descending target id); replaces *col by a new buffer.
 int sort_rows_desc(uint32_t **col, const int64_t *col_base_host, const int32_t *row_ptr, int64_t R,
                    int32_t P, int64_t nnz, hipStream_t st);
+// off[v] = sum of deg[u] for u < v (off has n + 1 entries; off[n] = total).
+int degree_offsets(const int32_t *deg, int64_t n, int64_t *off, hipStream_t st);
 }

@@ -1,5 +1,6 @@
-// Graph-build helper: sort every block row in descending order of target id
-// with rocPRIM's segmented radix sort. Setup only; the search never calls it.
+// Graph-build helpers: sort every block row in descending order of target id
+// with rocPRIM's segmented radix sort, and the offsets of the merged pull
+// rows (a scan of the degrees). Setup only; the search never calls them.
 // Descending rows let the parent search of a new vertex stop at its first
 // frontier neighbour, which is then the highest-labelled one.
 #include <algorithm>
@@ -68,6 +69,21 @@ int sort_rows_desc(uint32_t **col, const int64_t *col_base_host, const int32_t *
     }
     (void)hipFree(*col);
     *col = tmp;
+    return CSBFS_OK;
+}
+
+int degree_offsets(const int32_t *deg, int64_t n, int64_t *off, hipStream_t st) {
+    size_t ws_bytes = 0;
+    auto in = rocprim::make_transform_iterator(deg, [] __host__ __device__(int32_t d) { return (int64_t)d; });
+    CSBFS_HIP(rocprim::inclusive_scan(nullptr, ws_bytes, in, off + 1, (size_t)n, rocprim::plus<int64_t>(), st));
+    void *ws = nullptr;
+    CSBFS_HIP(hipMalloc(&ws, ws_bytes > 0 ? ws_bytes : 1));
+    hipError_t e = hipMemsetAsync(off, 0, sizeof(int64_t), st);
+    if (e == hipSuccess)
+        e = rocprim::inclusive_scan(ws, ws_bytes, in, off + 1, (size_t)n, rocprim::plus<int64_t>(), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(ws);
+    if (e != hipSuccess) return hip_fail(e, "degree_offsets", __FILE__, __LINE__);
     return CSBFS_OK;
 }
 
