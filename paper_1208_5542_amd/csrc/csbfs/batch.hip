@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kBThreads) void bexpand_kernel(BArgs a) {
         }
         wave_lds_sync();
     }
-    if (lane == 0 && edges) atomicAdd(a.edges, edges);
+    block_add<kBThreads / 64>(edges, a.edges);
 }
 
 __global__ __launch_bounds__(kBThreads) void bexpand_big_kernel(BArgs a) {
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kBThreads) void bexpand_big_kernel(BArgs a) {
             edges += (unsigned long long)(it.end - it.start);
         }
     }
-    if (lane == 0 && edges) atomicAdd(a.edges, edges);
+    block_add<kBThreads / 64>(edges, a.edges);
 }
 
 struct BUpdateArgs {
@@ -291,9 +291,11 @@ __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
     }
     if (lane < a.B && mine) atomicAdd(&cnt[lane], mine);
     __syncthreads();
-    if (threadIdx.x < a.B && cnt[threadIdx.x]) {
-        atomicAdd(&a.root_count[threadIdx.x], cnt[threadIdx.x]);
-        atomicAdd(a.total, cnt[threadIdx.x]);
+    if (threadIdx.x < a.B && cnt[threadIdx.x]) atomicAdd(&a.root_count[threadIdx.x], cnt[threadIdx.x]);
+    if (threadIdx.x == 0) {
+        unsigned long long sum = 0;
+        for (int r = 0; r < a.B; ++r) sum += cnt[r];
+        if (sum) atomicAdd(a.total, sum);
     }
 }
 

@@ -221,7 +221,6 @@ __device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int6
 template <bool kDense>
 __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
     if (*a.dir == kDirBU) return;
-    const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t ntiles = (a.rank_words + a.tile_words - 1) / a.tile_words;
@@ -231,7 +230,7 @@ __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
         expand_tile<kDense>(a, r, gt - (int64_t)r * ntiles, edges);
     }
     // `total` is wave-uniform, so every lane holds the wave's edge count
-    if (lane == 0 && edges) atomicAdd(a.edges, edges);
+    block_add<kExpThreads / 64>(edges, a.edges);
 }
 
 // Chunk-queue items (<= kBigChunk entries of one long row) of every
@@ -275,7 +274,7 @@ __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
             edges += (unsigned long long)(it.end - it.start);
         }
     }
-    if (lane == 0 && edges) atomicAdd(a.edges, edges);
+    block_add<kExpThreads / 64>(edges, a.edges);
 }
 
 struct PullArgs {
@@ -434,11 +433,8 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
         }
     }
     if (kBottomUp) {
-        for (int d = 32; d > 0; d >>= 1) read += __shfl_xor(read, d, 64);
-        if (lane == 0) {
-            if (read) atomicAdd(a.edges, read);
-            if (examined) atomicAdd(a.pulled, examined);
-        }
+        for (int d = 32; d > 0; d >>= 1) read += (unsigned long long)shfl64((int64_t)read, lane ^ d);
+        block_add<kPullThreads / 64>(read, a.edges, examined, a.pulled);
     }
 }
 
@@ -452,58 +448,65 @@ struct UpdateArgs {
     int64_t words;  // n / 64
     int64_t W;      // words per processor
     int32_t P;
-    unsigned long long *rank_count;  // [P]
     unsigned long long *total;       // [2]: frontier size, its adjacency entries
     uint32_t *ctrs;                  // [P]: chunk-queue counts, reset for the next level
     const int32_t *deg;              // [n]: adjacency entries per vertex
 };
 
+constexpr int kUpdWords = 16;  // bitmap words per wavefront step of the update
+
+// A wavefront takes kUpdWords consecutive bitmap words at a time: lane k
+// (< kUpdWords) handles word q0 + k (t = S & ~pi, pi = S, f = t); the wave
+// clears the P views at those words, then writes the level of every new
+// vertex word by word (lane = vertex) and reads its adjacency-entry count.
+// Branches on a word's t are uniform over the wave.
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
     const int lane = threadIdx.x & 63;
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    uint64_t t = 0;
-    if (q < a.words) {
-        // the new vertices of this word: seen in this level, not yet visited
-        // (S holds pi and every vertex the expansion discovered)
-        const uint64_t p = a.pi[q], sq = a.S[q];
-        t = sq & ~p;
-        if (t) a.pi[q] = sq;
-        a.f[q] = t;
-        // clear processor i's views (i, j) at the same offset for every j
-        const int64_t i = q / a.W, ql = q - i * a.W;
-        for (int32_t j = 0; j < a.P; ++j) a.view[(i * a.P + j) * a.W + ql] = 0;
-    }
-    if (q < a.P) a.ctrs[q] = 0;
-    const int c = __popcll(t);
-    const int64_t q0 = __shfl(q, 0, 64);
-    const int64_t q63 = q0 + 63 < a.words ? q0 + 63 : a.words - 1;
-    if (q0 / a.W == q63 / a.W) {
-        int s = c;
-        for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
-        if (lane == 0 && s && q0 < a.words) {
-            atomicAdd(&a.rank_count[q0 / a.W], (unsigned long long)s);
-            atomicAdd(&a.total[0], (unsigned long long)s);
+    if (blockIdx.x == 0 && threadIdx.x < a.P) a.ctrs[threadIdx.x] = 0;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned long long cnt = 0, dsum = 0;
+    for (int64_t q0 = wave * kUpdWords; q0 < a.words; q0 += nwaves * kUpdWords) {
+        const int64_t qk = q0 + lane;
+        uint64_t tk = 0;
+        if (lane < kUpdWords && qk < a.words) {
+            const uint64_t p = a.pi[qk], sq = a.S[qk];
+            tk = sq & ~p;
+            if (tk) a.pi[qk] = sq;
+            a.f[qk] = tk;
+            cnt += (unsigned long long)__popcll(tk);
         }
-    } else if (c) {
-        atomicAdd(&a.rank_count[q / a.W], (unsigned long long)c);
-        atomicAdd(&a.total[0], (unsigned long long)c);
-    }
-    // level of every new vertex, one coalesced row of 64 per non-zero word;
-    // the adjacency entries of the new frontier feed the direction choice
-    uint64_t nz = __ballot(t != 0);
-    unsigned long long dsum = 0;
-    while (nz) {
-        const int src = __ffsll((unsigned long long)nz) - 1;
-        nz &= nz - 1;
-        const uint64_t tw = __shfl(t, src, 64);
-        if ((tw >> lane) & 1) {
-            const int64_t v = ((q0 + src) << 6) + lane;
-            a.level[v] = a.next_level;
-            dsum += (unsigned long long)a.deg[v];
+        // processor i's views (i, j) at these words, kUpdWords consecutive per j
+        for (int idx = lane; idx < kUpdWords * a.P; idx += 64) {
+            const int64_t q = q0 + (idx % kUpdWords);
+            const int32_t j = idx / kUpdWords;
+            if (q < a.words) {
+                const int64_t i = q / a.W, ql = q - i * a.W;
+                a.view[(i * a.P + j) * a.W + ql] = 0;
+            }
         }
+        int32_t d[kUpdWords];
+#pragma unroll
+        for (int k = 0; k < kUpdWords; ++k) {
+            d[k] = 0;
+            const uint64_t t = (uint64_t)shfl64((int64_t)tk, k);
+            if (t) {
+                const int64_t v = ((q0 + k) << 6) + lane;
+                const int32_t dv = a.deg[v];
+                if ((t >> lane) & 1) {
+                    a.level[v] = a.next_level;
+                    d[k] = dv;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kUpdWords; ++k) dsum += (unsigned long long)d[k];
     }
-    for (int d = 32; d > 0; d >>= 1) dsum += __shfl_xor(dsum, d, 64);
-    if (lane == 0 && dsum) atomicAdd(&a.total[1], dsum);
+    for (int dd = 32; dd > 0; dd >>= 1) {
+        cnt += (unsigned long long)shfl64((int64_t)cnt, lane ^ dd);
+        dsum += (unsigned long long)shfl64((int64_t)dsum, lane ^ dd);
+    }
+    block_add<kUpdThreads / 64>(cnt, &a.total[0], dsum, &a.total[1]);
 }
 
 // Direction state carried from level to level on the device.
@@ -896,8 +899,8 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     // one resident wave per SIMD slot of every CU, a multiple of the XCD count
     const unsigned exp_grid = 2048, big_grid = 2048;
     const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
-    const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 16384);
-    const unsigned upd_grid = grid_for(words, kUpdThreads, 1u << 30);
+    const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 2048);
+    const unsigned upd_grid = grid_for((words + kUpdWords - 1) / kUpdWords, kUpdThreads / 64, 2048);
     DirArgs da{};
     da.st = e->dstate;
     da.n = n;
@@ -979,7 +982,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         // a2: mask, visit, f^{j+1}; a3: reduction of |f^{j+1}| and of its
         // adjacency entries; then the direction of level j + 1
         UpdateArgs ua{e->seen, e->pi, e->f, e->view, level, (int32_t)(j + 1), words, W,
-                      (int32_t)P, e->lc.rank + sn * P, e->lc.ctl + 2 * sn, e->ctrs, g->deg};
+                      (int32_t)P, e->lc.ctl + 2 * sn, e->ctrs, g->deg};
         hipLaunchKernelGGL(update_kernel, dim3(upd_grid), dim3(kUpdThreads), 0, st, ua);
         CSBFS_HIP(hipGetLastError());
         da.ctl = e->lc.ctl + 2 * sn;

@@ -87,6 +87,32 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Adds the workgroup's sum of v0 (and v1) to *d0 (and *d1) with one atomic
+// per workgroup: every lane of a wave holds its wave's value. Device-scope
+// atomics on one address are serialised at the memory side, so per-wave
+// atomics on a shared counter cost far more than this LDS reduction. Must be
+// reached by every thread of the workgroup.
+template <int kWaves>
+__device__ __forceinline__ void block_add(unsigned long long v0, unsigned long long *d0,
+                                          unsigned long long v1 = 0, unsigned long long *d1 = nullptr) {
+    __shared__ unsigned long long part[2][kWaves];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        part[0][w] = v0;
+        part[1][w] = v1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s0 = 0, s1 = 0;
+        for (int k = 0; k < kWaves; ++k) {
+            s0 += part[0][k];
+            s1 += part[1][k];
+        }
+        if (s0) atomicAdd(d0, s0);
+        if (d1 && s1) atomicAdd(d1, s1);
+    }
+}
+
 inline unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;
