@@ -317,6 +317,84 @@ int csbfs_batch_copy_stream(const csbfs_batch_engine *e, int32_t k, int32_t r, i
                             int32_t j, uint64_t *dst, int64_t cap_words, int64_t *n_words_out,
                             void *stream);
 
+/* Device bytes csbfs_batch_engine_create would allocate for these
+ * arguments (host only, allocates nothing). Returns -1 on bad arguments. */
+int64_t csbfs_batch_engine_bytes(const csbfs_graph *g, int32_t max_roots, int32_t max_levels,
+                                 uint32_t flags);
+
+/* ======================================================================== */
+/* Serving: a request loop over resident graphs.                             */
+/* ======================================================================== */
+
+/*
+ * A server answers breadth-first queries (graph, root) -> level[] over graphs
+ * registered with it (built once and resident in HBM). Requests wait in one
+ * queue; each of `slots` worker threads owns a HIP stream and, whenever it is
+ * free, takes the oldest waiting request together with up to max_batch - 1
+ * more waiting requests for the same graph and answers them with one batched
+ * search (csbfs_batch_bfs), so requests that arrive while others run are
+ * admitted as soon as a slot frees up, and the slots' batches overlap on the
+ * device. Batch engines are kept per (slot, graph) and admitted under an HBM
+ * budget: a batch starts only when its engine and result buffer fit next to
+ * the engines already held (idle engines are released, least recently used
+ * first, to make room). Every result equals that of a search from the same
+ * root alone (levels are exact; no parents are returned).
+ */
+typedef struct csbfs_server csbfs_server;
+
+typedef struct csbfs_server_config {
+    int32_t slots;       /* worker threads / HIP streams, 1..16 */
+    int32_t max_batch;   /* roots per batched search, 1..64 */
+    int32_t max_levels;  /* level counters of each engine, 1..65536 */
+    int32_t reserved;    /* 0 */
+    int64_t hbm_budget;  /* bytes of engines + result buffers the server may hold */
+} csbfs_server_config;
+
+/* Outcome of one request; times in seconds on one steady host clock. */
+typedef struct csbfs_request_info {
+    int64_t id;
+    int64_t root;
+    int32_t graph_id;
+    int32_t status;      /* CSBFS_OK or a negative status of the batch it ran in */
+    int32_t n_levels;    /* max level + 1 of this root's search */
+    int32_t batch_size;  /* requests answered by the same batched search */
+    int32_t slot;
+    int32_t reserved;
+    double t_submit;
+    double t_start;      /* its batch started */
+    double t_done;       /* its levels were in place */
+} csbfs_request_info;
+
+/* Start the workers. Errors: EINVAL (bad config), EHIP. */
+int csbfs_server_create(const csbfs_server_config *cfg, csbfs_server **out);
+
+/* Register a graph (must outlive the server); *graph_id = 0, 1, ... in the
+ * order of registration. Errors: EINVAL, ENOSPACE (one engine plus one
+ * result buffer of this graph exceed the budget). */
+int csbfs_server_add_graph(csbfs_server *s, const csbfs_graph *g, int32_t *graph_id);
+
+/*
+ * Queue a query. level_out: device int32[n of the graph] that receives the
+ * levels (-1 unreachable), or NULL for no copy-out; the caller keeps it valid
+ * until the request is done. Non-blocking; thread-safe. Errors: EINVAL
+ * (stopped server, unknown graph), ERANGE (root outside [0, n)).
+ */
+int csbfs_server_submit(csbfs_server *s, int32_t graph_id, int64_t root, int32_t *level_out,
+                        int64_t *request_id);
+
+/* Block until the request is done and return its outcome (once per id).
+ * Errors: EINVAL (unknown or already collected id). */
+int csbfs_server_wait(csbfs_server *s, int64_t request_id, csbfs_request_info *info);
+
+/* Block until no request is waiting or running. */
+int csbfs_server_drain(csbfs_server *s);
+
+/* Device bytes currently held by the server's engines and buffers. */
+int64_t csbfs_server_bytes_held(const csbfs_server *s);
+
+/* Drain, stop the workers and release everything. NULL is accepted. */
+int csbfs_server_free(csbfs_server *s);
+
 /* ======================================================================== */
 /* WAH-64 codec on device buffers (Sec. IV).                                */
 /* ======================================================================== */

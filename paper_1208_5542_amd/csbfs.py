@@ -50,6 +50,21 @@ class LevelStats(ctypes.Structure):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("hbm_budget", ctypes.c_int64)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("root", ctypes.c_int64), ("graph_id", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("slot", ctypes.c_int32), ("reserved", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "reserved"}
+
+
 def lib():
     """Load libcsbfs.so (after torch, so that one HIP runtime serves both)."""
     global _lib
@@ -86,6 +101,14 @@ def lib():
         "csbfs_batch_stream_words": ([vp, vp, i32], ctypes.c_int),
         "csbfs_batch_copy_stream": ([vp, i32, i32, i32, i32, vp, i64, ctypes.POINTER(i64), vp],
                                     ctypes.c_int),
+        "csbfs_batch_engine_bytes": ([vp, i32, i32, u32], i64),
+        "csbfs_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], ctypes.c_int),
+        "csbfs_server_add_graph": ([vp, vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "csbfs_server_submit": ([vp, i32, i64, vp, ctypes.POINTER(i64)], ctypes.c_int),
+        "csbfs_server_wait": ([vp, i64, ctypes.POINTER(RequestInfo)], ctypes.c_int),
+        "csbfs_server_drain": ([vp], ctypes.c_int),
+        "csbfs_server_bytes_held": ([vp], i64),
+        "csbfs_server_free": ([vp], ctypes.c_int),
         "csbfs_wah_capacity": ([i64], i64),
         "csbfs_wah_workspace_bytes": ([i64], sz),
         "csbfs_wah_encode": ([vp, vp, i64, vp, i64, vp, vp, sz, vp], ctypes.c_int),
@@ -316,6 +339,57 @@ class BatchEngine:
         _check(lib().csbfs_batch_copy_stream(self._h, k, r, i, j, _ptr(out), cap, ctypes.byref(nw),
                                              _stream(stream)), "csbfs_batch_copy_stream")
         return out[: int(nw.value)]
+
+
+class Server:
+    """Request loop over resident graphs (csbfs_server_*): continuous batching
+    of queries into up to `slots` concurrent batched searches, engines admitted
+    under an HBM budget."""
+
+    def __init__(self, slots: int = 2, max_batch: int = 64, max_levels: int = 256,
+                 hbm_budget: int = 32 << 30):
+        cfg = ServerConfig(slots, max_batch, max_levels, 0, hbm_budget)
+        h = ctypes.c_void_p()
+        _check(lib().csbfs_server_create(ctypes.byref(cfg), ctypes.byref(h)), "csbfs_server_create")
+        self._h = h
+        self.graphs: list[Graph] = []
+
+    def add_graph(self, graph: Graph) -> int:
+        gid = ctypes.c_int32()
+        _check(lib().csbfs_server_add_graph(self._h, graph.handle, ctypes.byref(gid)), "csbfs_server_add_graph")
+        self.graphs.append(graph)
+        return int(gid.value)
+
+    def submit(self, graph_id: int, root: int, out: torch.Tensor | None = None) -> int:
+        """Queue a query; `out` (device int32[n]) receives the levels."""
+        if out is not None:
+            assert out.dtype == torch.int32 and out.numel() == self.graphs[graph_id].n
+        rid = ctypes.c_int64()
+        _check(lib().csbfs_server_submit(self._h, graph_id, int(root), _ptr(out), ctypes.byref(rid)),
+               "csbfs_server_submit")
+        return int(rid.value)
+
+    def wait(self, request_id: int) -> dict:
+        info = RequestInfo()
+        _check(lib().csbfs_server_wait(self._h, request_id, ctypes.byref(info)), "csbfs_server_wait")
+        return info.as_dict()
+
+    def drain(self):
+        _check(lib().csbfs_server_drain(self._h), "csbfs_server_drain")
+
+    def bytes_held(self) -> int:
+        return int(lib().csbfs_server_bytes_held(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().csbfs_server_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def wah_capacity(nbits: int) -> int:

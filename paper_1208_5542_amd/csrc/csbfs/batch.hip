@@ -386,6 +386,47 @@ void bengine_release(csbfs_batch_engine *e) {
 
 }  // namespace
 
+namespace {
+
+// Device bytes of every buffer csbfs_batch_engine_create allocates.
+struct BatchSizes {
+    int64_t vis, nx, f, view, arena, seg, chunk, queue, qoff, qcount, roots, status, counters;
+    int64_t total() const {
+        return vis + nx + f + view + arena + 2 * seg + chunk + queue + qoff + qcount + roots + status + counters;
+    }
+};
+
+BatchSizes batch_sizes(const csbfs_graph *g, int64_t B, int64_t L, uint32_t flags) {
+    const int64_t P = g->P, n = g->n;
+    const int64_t Smax = B * P * P, slots = L + 1;
+    const int64_t arena_slots = (flags & CSBFS_FLAG_KEEP_STREAMS) ? slots : 1;
+    int64_t items = 0;
+    for (int64_t r = 0; r < P; ++r) items += g->big_items[r];
+    BatchSizes z{};
+    z.vis = 8 * n;
+    z.nx = 8 * n;
+    z.f = 8 * B * (n / 64);
+    z.view = 8 * B * P * (n / 64);
+    z.arena = 8 * Smax * wah_cap(g->R) * arena_slots;
+    z.seg = 4 * Smax * enc_segments(g->R);
+    z.chunk = 8 * Smax * dec_chunks(g->R);
+    z.queue = (int64_t)sizeof(BItem) * (items > 0 ? items : 1);
+    z.qoff = 8 * (P + 1);
+    z.qcount = 4 * P;
+    z.roots = 8 * B;
+    z.status = 4;
+    z.counters = 8 * slots * (1 + B + 1 + Smax + B * P) + 8 * slots * Smax;
+    return z;
+}
+
+}  // namespace
+
+extern "C" int64_t csbfs_batch_engine_bytes(const csbfs_graph *g, int32_t max_roots, int32_t max_levels,
+                                            uint32_t flags) {
+    if (!g || max_roots < 1 || max_roots > kMaxRoots || max_levels < 1 || max_levels > 65536) return -1;
+    return batch_sizes(g, max_roots, max_levels, flags).total();
+}
+
 extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots, int32_t max_levels,
                                          uint32_t flags, csbfs_batch_engine **out) {
     if (!out) return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: out is NULL");
@@ -410,7 +451,6 @@ extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots
     e->nchunk = dec_chunks(g->R);
     e->Smax = B * P * P;
     const int64_t slots = (int64_t)max_levels + 1;
-    const int64_t arena_slots = (flags & CSBFS_FLAG_KEEP_STREAMS) ? slots : 1;
     std::vector<int64_t> qoff(P + 1, 0);
     for (int64_t r = 0; r < P; ++r) qoff[r + 1] = qoff[r] + g->big_items[r];
     auto alloc = [&](void **p, size_t bytes) -> int {
@@ -429,21 +469,21 @@ extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots
         }                                                                  \
         ptr = reinterpret_cast<decltype(ptr)>(_p);                         \
     } while (0)
-    BALLOC(e->vis, sizeof(uint64_t) * n);
-    BALLOC(e->nx, sizeof(uint64_t) * n);
-    BALLOC(e->f, sizeof(uint64_t) * B * (n / 64));
-    BALLOC(e->view, sizeof(uint64_t) * B * P * (n / 64));
-    BALLOC(e->arena, sizeof(uint64_t) * e->Smax * e->cap * arena_slots);
-    BALLOC(e->seg_count, sizeof(int32_t) * e->Smax * e->nseg);
-    BALLOC(e->seg_first, sizeof(int32_t) * e->Smax * e->nseg);
-    BALLOC(e->chunk_groups, sizeof(int64_t) * e->Smax * e->nchunk);
-    BALLOC(e->queue, sizeof(BItem) * (qoff[P] > 0 ? qoff[P] : 1));
-    BALLOC(e->qoff, sizeof(int64_t) * (P + 1));
-    BALLOC(e->qcount, sizeof(uint32_t) * P);
-    BALLOC(e->roots_dev, sizeof(int64_t) * B);
-    BALLOC(e->status, sizeof(int32_t));
-    const size_t cnt_bytes = sizeof(unsigned long long) * slots * (1 + B + 1 + e->Smax + B * P) +
-                             sizeof(int64_t) * slots * e->Smax;
+    const BatchSizes z = batch_sizes(g, B, max_levels, flags);
+    BALLOC(e->vis, z.vis);
+    BALLOC(e->nx, z.nx);
+    BALLOC(e->f, z.f);
+    BALLOC(e->view, z.view);
+    BALLOC(e->arena, z.arena);
+    BALLOC(e->seg_count, z.seg);
+    BALLOC(e->seg_first, z.seg);
+    BALLOC(e->chunk_groups, z.chunk);
+    BALLOC(e->queue, z.queue);
+    BALLOC(e->qoff, z.qoff);
+    BALLOC(e->qcount, z.qcount);
+    BALLOC(e->roots_dev, z.roots);
+    BALLOC(e->status, z.status);
+    const size_t cnt_bytes = (size_t)z.counters;
     BALLOC(e->counters_mem, cnt_bytes);
 #undef BALLOC
     e->counters_bytes = cnt_bytes;

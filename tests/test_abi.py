@@ -67,6 +67,20 @@ def test_host_side_argument_checks(lib):
     assert lib.csbfs_batch_bfs(None, None, 0, None, None, 0, None, None) == -1
     assert lib.csbfs_batch_stream_words(None, None, 0) == -1
     assert lib.csbfs_batch_engine_free(None) == 0
+    assert lib.csbfs_batch_engine_bytes(None, 64, 64, 0) == -1
+    # serving: configuration checks happen before any device call
+    from paper_1208_5542_amd import csbfs as cb
+    for bad in ((0, 64, 64, 0, 1 << 30), (17, 64, 64, 0, 1 << 30), (1, 0, 64, 0, 1 << 30),
+                (1, 65, 64, 0, 1 << 30), (1, 64, 0, 0, 1 << 30), (1, 64, 64, 1, 1 << 30), (1, 64, 64, 0, 0)):
+        cfg = cb.ServerConfig(*bad)
+        assert lib.csbfs_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1, bad
+    assert lib.csbfs_server_create(None, ctypes.byref(h)) == -1
+    assert lib.csbfs_server_add_graph(None, None, None) == -1
+    assert lib.csbfs_server_submit(None, 0, 0, None, None) == -1
+    assert lib.csbfs_server_wait(None, 0, None) == -1
+    assert lib.csbfs_server_drain(None) == -1
+    assert lib.csbfs_server_bytes_held(None) == -1
+    assert lib.csbfs_server_free(None) == 0
     assert lib.csbfs_bfs(None, 0, None, None, None, 0, None, None) == -1
     assert lib.csbfs_engine_stream_words(None, None, 0) == -1
     assert lib.csbfs_engine_copy_stream(None, 0, 0, 0, None, 0, None, None) == -1
@@ -89,6 +103,20 @@ def test_package_import_does_not_need_a_gpu():
     import paper_1208_5542_amd.csbfs as m
     importlib.reload(m)
     assert m.FLAG_TIMING == 1 and m.FLAG_DENSE_ONLY == 16 and m.FLAG_BOTTOM_UP_ONLY == 32
+
+
+def _struct_fields(name):
+    text = open(HEADER).read()
+    body = text[text.index(f"typedef struct {name} {{"):text.index(f"}} {name};")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return re.findall(r"\b(?:int64_t|int32_t|float|double)\s+(\w+);", body)
+
+
+def test_server_structs_match_header():
+    from paper_1208_5542_amd import csbfs
+    assert _struct_fields("csbfs_server_config") == [f[0] for f in csbfs.ServerConfig._fields_]
+    assert _struct_fields("csbfs_request_info") == [f[0] for f in csbfs.RequestInfo._fields_]
+    assert ctypes.sizeof(csbfs.ServerConfig) == 24 and ctypes.sizeof(csbfs.RequestInfo) == 64
 
 
 def test_level_stats_layout_matches_header():
