@@ -15,8 +15,9 @@ tuples in the reached component / search time), compression ratios over all
 messages, the expansion step's roofline against HBM bandwidth (algorithmic
 bytes from the level statistics, time from HIP events recorded on the
 library's stream), the batched comparison (64 roots in one batched search
-against the same roots one at a time, R-MAT scale 24) and the CPU oracle
-timed on a bounded sample.
+against the same roots one at a time, R-MAT scale 24), the serving run
+(Poisson queries over a resident pool of six graphs: p50/p99 latency and
+GTEPS) and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -56,6 +57,10 @@ def parse():
                     help="workload of the batched comparison (64 roots in one search)")
     ap.add_argument("--batch-reps", type=int, default=3, help="timed batches")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-qps", type=float, default=2000.0, help="Poisson arrival rate of the serving run")
+    ap.add_argument("--serve-requests", type=int, default=4000, help="queries of the serving run")
+    ap.add_argument("--serve-slots", type=int, default=4, help="concurrent batched searches")
     ap.add_argument("--json-out", default=None, help="also write a detailed report here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
@@ -209,6 +214,94 @@ def batched_section(args):
     return out
 
 
+SERVING_POOL = [("rmat16", 16), ("rmat18", 18), ("rmat20", 20), ("rmat22", 22), ("rmat24", 24), ("er20", 20)]
+
+
+def serving_section(args):
+    """Queries at Poisson arrival times over a resident pool (R-MAT scales
+    16-24 and an Erdos-Renyi graph of 2^20 vertices and 8 * 2^20 tuples,
+    average degree 16; all on a 4 x 4 grid), each for a uniformly drawn
+    graph and root, served by the continuous-batching loop. Latency is
+    submit-to-done on the server's clock; GTEPS is the sum over queries of
+    the reached component's tuples over the span from the first submit to
+    the last completion."""
+    import numpy as np
+    import torch
+
+    from paper_1208_5542_amd import csbfs, inputs
+
+    t0 = time.perf_counter()
+    pool = []
+    for name, scale in SERVING_POOL:
+        n = 1 << scale
+        if name.startswith("er"):
+            src, dst = inputs.er_tuples(n, 8 * n, inputs.graph_seed(scale) + 0xE)
+        else:
+            src, dst = inputs.rmat_tuples(scale, 16)
+        g = csbfs.Graph(torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), n, 4)
+        roots = [int(r) for r in inputs.pick_roots(n, src, dst, 128, inputs.graph_seed(scale) + 3)]
+        del src, dst
+        # traversed tuples per root (TEPS numerator), from one search each
+        eng = csbfs.Engine(g, max_levels=256)
+        level = torch.empty(n, dtype=torch.int32, device="cuda")
+        parent = torch.empty(n, dtype=torch.int32, device="cuda")
+        m = []
+        for r in roots:
+            eng.bfs(r, level, parent, with_stats=False)
+            m.append(g.traversed_tuples(level))
+        del eng, level, parent
+        pool.append(dict(name=name, n=n, g=g, roots=roots, m=m))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"[bench] serving: pool of {len(pool)} graphs ready in {time.perf_counter() - t0:.1f}s")
+
+    budget = 48 << 30
+    server = csbfs.Server(slots=args.serve_slots, max_batch=64, max_levels=256, hbm_budget=budget)
+    gids = [server.add_graph(e["g"]) for e in pool]
+    rng = np.random.default_rng(0x5E5E)
+    # warm-up: one batch per graph so engines exist before the timed stream
+    for e, gid in zip(pool, gids):
+        server.wait(server.submit(gid, e["roots"][0]))
+    gaps = rng.exponential(1.0 / args.serve_qps, args.serve_requests)
+    picks = [(int(rng.integers(len(pool))), int(rng.integers(128))) for _ in range(args.serve_requests)]
+    ids, meta = [], []
+    start = time.perf_counter()
+    due = start
+    for gap, (gi, ri) in zip(gaps, picks):
+        due += gap
+        delay = due - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(server.submit(gids[gi], pool[gi]["roots"][ri]))
+        meta.append((gi, ri))
+    infos = [server.wait(i) for i in ids]
+    server.close()
+    bad = sum(1 for i in infos if i["status"] != 0)
+    lat = np.array([i["t_done"] - i["t_submit"] for i in infos]) * 1e3
+    span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+    m_tot = sum(pool[gi]["m"][ri] for gi, ri in meta)
+    per_graph = {}
+    for (gi, _), l in zip(meta, lat):
+        per_graph.setdefault(pool[gi]["name"], []).append(l)
+    out = {
+        "pool": [f"{e['name']} (n={e['n']}, p=4)" for e in pool],
+        "requests": len(infos), "failed": bad, "offered_qps": args.serve_qps,
+        "achieved_qps": round(len(infos) / span, 1),
+        "slots": args.serve_slots, "max_batch": 64, "hbm_budget_bytes": budget,
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
+        "latency_p50_ms_by_graph": {k: round(float(np.percentile(v, 50)), 3) for k, v in per_graph.items()},
+        "gteps": round(m_tot / span / 1e9, 4),
+        "mean_batch": round(float(np.mean([i["batch_size"] for i in infos])), 2),
+    }
+    log(f"[bench] serving: {out['achieved_qps']} qps, p50 {out['latency_ms']['p50']} ms, "
+        f"p99 {out['latency_ms']['p99']} ms, {out['gteps']} GTEPS, mean batch {out['mean_batch']}")
+    del pool
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -319,6 +412,33 @@ def main():
         ratio = raw_self / max(tot["self_bytes"], 1)
         sieve_gain = None
         c_factor = None
+    # mode switch (Table 5: BIT / WAH / DIR-WAH) beside a Table-2 sparse vector,
+    # per level summed over the timed roots: Alg. 1 sends every piece as a
+    # raw bitmap, Alg. 2 its WAH stream, Alg. 3 the sieved WAH stream; a
+    # sparse vector sends 8-byte ids of the piece to the p - 1 others
+    by_level = {}
+    for _, _nl, stats, _m in per_root:
+        for k, st_ in enumerate(stats):
+            if k == 0:
+                continue  # seeded, never sent
+            d = by_level.setdefault(k, {"frontier": 0, "bit": 0, "wah": 0, "dir_wah": 0, "sparse": 0})
+            d["frontier"] += st_["frontier"]
+            d["bit"] += st_["raw_bytes"]
+            d["wah"] += st_["wah_unsieved_bytes"]
+            d["dir_wah"] += st_["wah_sieved_bytes"]
+            d["sparse"] += 8 * (p - 1) * st_["frontier"]
+    mode_levels, switch_total = [], 0
+    for k in sorted(by_level):
+        d = by_level[k]
+        best = min(("bit", "wah", "dir_wah", "sparse"), key=lambda x: d[x])
+        switch_total += d[best]
+        mode_levels.append(dict(level=k, **d, cheapest=best))
+    mode_switch = {
+        "levels": mode_levels,
+        "total": {x: sum(d[x] for d in by_level.values()) for x in ("bit", "wah", "dir_wah", "sparse")},
+        "per_level_cheapest_total": switch_total,
+        "note": "bytes sent between processors (i != j) over all timed roots; level 0 is seeded",
+    } if p > 1 else None
     achieved = exp_bytes / (exp_ms / 1e3) / 1e9 if exp_ms > 0 else 0.0
     bpl = exp_bytes / max(exp_launches, 1)
     traffic = load_traffic(wl.name)
@@ -348,6 +468,7 @@ def main():
                   "bits_before_sieve": tot["unsieved_bits"], "bits_after_sieve": tot["sieved_bits"]},
         "time_split_ms": {k: round(v / args.steps, 4) for k, v in cat_ms.items()},
         "levels_by_direction": dir_count,
+        "mode_switch": mode_switch,
         "roofline": {"bound": "hbm",
                      "kernel": "expansion step (expand_kernel + expand_big_kernel, or pull_kernel<bottom-up>)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -361,6 +482,8 @@ def main():
         del eng, probe, g, level, parent
         torch.cuda.empty_cache()
         out["batched"] = batched_section(args)
+    if not args.no_serving:
+        out["serving"] = serving_section(args)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(n, src, dst, p, roots[args.warmup:], args.cpu_seconds)
