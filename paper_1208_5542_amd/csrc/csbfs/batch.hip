@@ -1,7 +1,9 @@
 // Batched searches: Algorithm 3 (Sec. V.B) for up to 64 roots at once.
 //
 // Vertex v carries a visit mask vis[v] (bit r: reached by root r) and, during
-// a level, a mask nx[v] of the roots that discovered it. Each root keeps its
+// a level, a mask nx[v] of the roots that discovered it; the two are stored
+// side by side (vn[2v], vn[2v+1]) so that one 16-byte access serves the
+// push's check of both. Each root keeps its
 // own frontier bitmap: plane r of `f` holds f_r, and plane r of the views
 // holds the pieces P_i received for root r. One level:
 //
@@ -48,8 +50,7 @@ struct BArgs {
     const int32_t *row_ptr;
     const int64_t *col_base;
     const uint32_t *col;
-    const uint64_t *vis;  // [n]
-    uint64_t *nx;         // [n]
+    uint64_t *vn;         // [n][2]: visit mask, discovery mask
     BItem *queue;
     const int64_t *qoff;     // [P + 1]
     uint32_t *queue_count;   // [P]
@@ -63,16 +64,17 @@ struct BArgs {
 // Push kBUnroll (target v, root mask m) pairs; loads first, then atomics.
 __device__ __forceinline__ void brelax(const BArgs &a, const int64_t (&v)[kBUnroll],
                                        const uint64_t (&m)[kBUnroll], const bool (&ok)[kBUnroll]) {
-    uint64_t add[kBUnroll];
-#pragma unroll
-    for (int k = 0; k < kBUnroll; ++k) add[k] = ok[k] ? (m[k] & ~a.vis[v[k]]) : 0ull;
-    uint64_t have[kBUnroll];
-#pragma unroll
-    for (int k = 0; k < kBUnroll; ++k)
-        have[k] = add[k] ? __hip_atomic_load(&a.nx[v[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ~0ull;
+    // one 16-byte load per target: its visit mask and a (possibly stale)
+    // view of its discovery mask, which only saves redundant atomics
+    ulonglong2 w[kBUnroll];
 #pragma unroll
     for (int k = 0; k < kBUnroll; ++k)
-        if (add[k] & ~have[k]) atomicOr((unsigned long long *)&a.nx[v[k]], (unsigned long long)add[k]);
+        w[k] = ok[k] ? *reinterpret_cast<const ulonglong2 *>(a.vn + 2 * v[k]) : make_ulonglong2(~0ull, ~0ull);
+#pragma unroll
+    for (int k = 0; k < kBUnroll; ++k) {
+        const uint64_t add = m[k] & ~w[k].x;
+        if (add & ~w[k].y) atomicOr((unsigned long long *)(a.vn + 2 * v[k] + 1), (unsigned long long)add);
+    }
 }
 
 // A wave's tile: kBTile consecutive words of every root plane. Loads and
@@ -225,8 +227,7 @@ __global__ __launch_bounds__(kBThreads) void bexpand_big_kernel(BArgs a) {
 }
 
 struct BUpdateArgs {
-    uint64_t *vis;
-    uint64_t *nx;
+    uint64_t *vn;      // [n][2]
     uint64_t *f;       // [B][n / 64] planes of the new frontier
     int32_t *level;    // [B][n]
     int32_t next_level;
@@ -261,13 +262,12 @@ __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
             uint64_t plane = 0;
             if (q < words) {
                 const int64_t v = (q << 6) + lane;
-                const uint64_t nxv = a.nx[v];
+                ulonglong2 *pv = reinterpret_cast<ulonglong2 *>(a.vn + 2 * v);
+                const ulonglong2 w = *pv;
                 uint64_t nw = 0;
-                if (nxv) {
-                    a.nx[v] = 0;
-                    const uint64_t visv = a.vis[v];
-                    nw = nxv & ~visv;
-                    if (nw) a.vis[v] = visv | nw;
+                if (w.y) {
+                    nw = w.y & ~w.x;
+                    *pv = make_ulonglong2(w.x | nw, 0ull);
                 }
                 // lane r collects root r's frontier word: bit b = vertex q*64+b is new for r
                 for (uint64_t it = wave_or64(nw); it; it &= it - 1) {
@@ -300,8 +300,7 @@ __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
 }
 
 struct BSeedArgs {
-    uint64_t *vis;
-    uint64_t *nx;
+    uint64_t *vn;      // [n][2]
     uint64_t *view;
     int64_t view_words;  // all planes
     int32_t *level;
@@ -313,10 +312,7 @@ __global__ void bseed_fill_kernel(BSeedArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t top = a.view_words > a.level_words ? a.view_words : a.level_words;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < top; k += stride) {
-        if (k < a.n) {
-            a.vis[k] = 0;
-            a.nx[k] = 0;
-        }
+        if (k < a.n) reinterpret_cast<ulonglong2 *>(a.vn)[k] = make_ulonglong2(0ull, 0ull);
         if (k < a.view_words) a.view[k] = 0;
         if (k < a.level_words) a.level[k] = -1;
     }
@@ -330,7 +326,7 @@ __global__ void bseed_root_kernel(BSeedArgs a, const int64_t *roots, int32_t B, 
     if (r >= B) return;
     const int64_t s = roots[r];
     const int64_t own = s / R, sl = s - own * R;
-    atomicOr((unsigned long long *)&a.vis[s], 1ull << r);
+    atomicOr((unsigned long long *)(a.vn + 2 * s), 1ull << r);
     a.level[(int64_t)r * a.n + s] = 0;
     for (int32_t i = 0; i < P; ++i)
         a.view[r * vplane + ((int64_t)i * P + own) * W + (sl >> 6)] = 1ull << (sl & 63);
@@ -348,7 +344,7 @@ struct csbfs_batch_engine {
     int32_t Bmax = 0, L = 0;
     uint32_t flags = 0;
     int64_t cap = 0, nseg = 0, nchunk = 0, Smax = 0;
-    uint64_t *vis = nullptr, *nx = nullptr, *f = nullptr, *view = nullptr, *arena = nullptr;
+    uint64_t *vn = nullptr, *f = nullptr, *view = nullptr, *arena = nullptr;
     int32_t *seg_count = nullptr, *seg_first = nullptr;
     int64_t *chunk_groups = nullptr;
     BItem *queue = nullptr;
@@ -403,8 +399,8 @@ BatchSizes batch_sizes(const csbfs_graph *g, int64_t B, int64_t L, uint32_t flag
     int64_t items = 0;
     for (int64_t r = 0; r < P; ++r) items += g->big_items[r];
     BatchSizes z{};
-    z.vis = 8 * n;
-    z.nx = 8 * n;
+    z.vis = 16 * n;
+    z.nx = 0;
     z.f = 8 * B * (n / 64);
     z.view = 8 * B * P * (n / 64);
     z.arena = 8 * Smax * wah_cap(g->R) * arena_slots;
@@ -470,8 +466,7 @@ extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots
         ptr = reinterpret_cast<decltype(ptr)>(_p);                         \
     } while (0)
     const BatchSizes z = batch_sizes(g, B, max_levels, flags);
-    BALLOC(e->vis, z.vis);
-    BALLOC(e->nx, z.nx);
+    BALLOC(e->vn, z.vis);
     BALLOC(e->f, z.f);
     BALLOC(e->view, z.view);
     BALLOC(e->arena, z.arena);
@@ -546,7 +541,7 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
     CSBFS_HIP(hipMemsetAsync(e->status, 0, sizeof(int32_t), st));
     CSBFS_HIP(hipMemsetAsync(e->qcount, 0, sizeof(uint32_t) * P, st));
     CSBFS_HIP(hipMemcpyAsync(e->roots_dev, roots, sizeof(int64_t) * B, hipMemcpyHostToDevice, st));
-    BSeedArgs sa{e->vis, e->nx, e->view, B * vplane, level, B * n, n};
+    BSeedArgs sa{e->vn, e->view, B * vplane, level, B * n, n};
     const int64_t fill = B * n > B * vplane ? B * n : B * vplane;
     hipLaunchKernelGGL(bseed_fill_kernel, dim3(grid_for(fill, 256, 16384)), dim3(256), 0, st, sa);
     CSBFS_HIP(hipGetLastError());
@@ -561,8 +556,7 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
     ea.row_ptr = g->row_ptr;
     ea.col_base = g->col_base;
     ea.col = g->col;
-    ea.vis = e->vis;
-    ea.nx = e->nx;
+    ea.vn = e->vn;
     ea.queue = e->queue;
     ea.qoff = e->qoff;
     ea.queue_count = e->qcount;
@@ -622,7 +616,7 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
         hipLaunchKernelGGL(bexpand_big_kernel, dim3(grid), dim3(kBThreads), 0, st, ea);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
-        BUpdateArgs ua{e->vis, e->nx, e->f, level, (int32_t)(j + 1), (int32_t)B, n,
+        BUpdateArgs ua{e->vn, e->f, level, (int32_t)(j + 1), (int32_t)B, n,
                        e->rootc + sn * Bm, e->ctl + sn, e->qcount, (int32_t)P};
         hipLaunchKernelGGL(bupdate_kernel, dim3(grid_for((words + kBTile - 1) / kBTile, kBThreads / 64, 2048)), dim3(kBThreads), 0, st, ua);
         CSBFS_HIP(hipGetLastError());
