@@ -219,8 +219,7 @@ __device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int6
 // queue (one wave-aggregated reservation); the remaining edges of the 64
 // sources are spread evenly over the lanes, kUnroll edges per lane per step.
 template <bool kDense>
-__global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
-    if (*a.dir == kDirBU) return;
+__device__ __forceinline__ void expand_body(const ExpandArgs &a) {
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t ntiles = (a.rank_words + a.tile_words - 1) / a.tile_words;
@@ -231,6 +230,12 @@ __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
     }
     // `total` is wave-uniform, so every lane holds the wave's edge count
     block_add<kExpThreads / 64>(edges, a.edges);
+}
+
+template <bool kDense>
+__global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
+    if (*a.dir == kDirBU) return;
+    expand_body<kDense>(a);
 }
 
 // Chunk-queue items (<= kBigChunk entries of one long row) of every
@@ -313,8 +318,7 @@ struct PullArgs {
 // step; lanes still searching after kPullRounds steps are finished by the
 // whole wave, 64 entries per step.
 template <bool kBottomUp>
-__global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
-    if (kBottomUp && *a.dir != kDirBU) return;
+__device__ __forceinline__ void pull_body(const PullArgs &a) {
     __shared__ unsigned long long found_bits[kPullThreads / 64][kPullTileBU];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
@@ -438,6 +442,62 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
     }
 }
 
+template <bool kBottomUp>
+__global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
+    if (kBottomUp && *a.dir != kDirBU) return;
+    pull_body<kBottomUp>(a);
+}
+
+// One launch per level for the default (direction-optimizing) search: the
+// top-down push or the bottom-up pull, as the level's direction says.
+static_assert(kExpThreads == kPullThreads, "one block size for both directions");
+__global__ __launch_bounds__(kExpThreads) void level_kernel(ExpandArgs ea, PullArgs pa) {
+    if (*ea.dir == kDirBU)
+        pull_body<true>(pa);
+    else
+        expand_body<false>(ea);
+}
+
+// Direction state carried from level to level on the device.
+struct DirState {
+    int32_t cur;              // direction of the level expanded next
+    int32_t pad;
+    unsigned long long vdeg;  // adjacency entries of the visited vertices
+    unsigned long long prev;  // size of the frontier before the newest one
+};
+
+struct DirArgs {
+    DirState *st;
+    int32_t *rec;   // direction recorded for level k + 1
+    int64_t n;
+    int64_t nnz;
+    float alpha;
+    float beta;
+    int32_t force;  // < 0: choose by the rule; else this direction at every level
+};
+
+// Beamer's rule (Sec. VIII names direction optimization as the next step):
+// m_f = entries of the new frontier, m_u = entries of unvisited vertices.
+// Top-down turns bottom-up when m_f * alpha > m_u; bottom-up turns top-down
+// when the frontier is below n / beta and shrinking. One thread.
+__device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsigned long long mf) {
+    DirState s = *a.st;
+    s.vdeg += mf;
+    const double mu = (double)a.nnz - (double)s.vdeg;
+    int32_t next = s.cur;
+    if (a.force >= 0) {
+        next = a.force;
+    } else if (s.cur == kDirTD) {
+        if (a.alpha > 0.f && (double)mf * (double)a.alpha > mu) next = kDirBU;
+    } else if ((double)nf * (double)a.beta < (double)a.n && nf < s.prev) {
+        next = kDirTD;
+    }
+    s.prev = nf;
+    s.cur = next;
+    *a.st = s;
+    *a.rec = next;
+}
+
 struct UpdateArgs {
     const uint64_t *S;
     uint64_t *pi;
@@ -451,15 +511,21 @@ struct UpdateArgs {
     unsigned long long *total;       // [2]: frontier size, its adjacency entries
     uint32_t *ctrs;                  // [P]: chunk-queue counts, reset for the next level
     const int32_t *deg;              // [n]: adjacency entries per vertex
+    unsigned long long *part;        // [gridDim][2]: per-workgroup sums
+    uint32_t *ticket;                // workgroups done; 0 between levels
+    DirArgs dir;
 };
 
-constexpr int kUpdWords = 16;  // bitmap words per wavefront step of the update
+constexpr int kUpdWords = 16;     // bitmap words per wavefront step of the update
+constexpr int kUpdMaxBlocks = 512;  // workgroups of the update (their sums meet in one)
 
 // A wavefront takes kUpdWords consecutive bitmap words at a time: lane k
 // (< kUpdWords) handles word q0 + k (t = S & ~pi, pi = S, f = t); the wave
 // clears the P views at those words, then writes the level of every new
 // vertex word by word (lane = vertex) and reads its adjacency-entry count.
-// Branches on a word's t are uniform over the wave.
+// Branches on a word's t are uniform over the wave. Each workgroup stores
+// its sums; the last one to finish adds them up, stores the level's
+// counters and chooses the next level's direction.
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
     const int lane = threadIdx.x & 63;
     if (blockIdx.x == 0 && threadIdx.x < a.P) a.ctrs[threadIdx.x] = 0;
@@ -506,50 +572,54 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
         cnt += (unsigned long long)shfl64((int64_t)cnt, lane ^ dd);
         dsum += (unsigned long long)shfl64((int64_t)dsum, lane ^ dd);
     }
-    block_add<kUpdThreads / 64>(cnt, &a.total[0], dsum, &a.total[1]);
-}
-
-// Direction state carried from level to level on the device.
-struct DirState {
-    int32_t cur;              // direction of the level expanded next
-    int32_t pad;
-    unsigned long long vdeg;  // adjacency entries of the visited vertices
-    unsigned long long prev;  // size of the frontier before the newest one
-};
-
-struct DirArgs {
-    DirState *st;
-    const unsigned long long *ctl;  // [2]: |f^{k+1}|, its adjacency entries
-    int32_t *rec;                   // direction recorded for level k + 1
-    int64_t n;
-    int64_t nnz;
-    float alpha;
-    float beta;
-    int32_t force;  // < 0: choose by the rule; else this direction at every level
-};
-
-// Beamer's rule (Sec. VIII names direction optimization as the next step):
-// m_f = entries of the new frontier, m_u = entries of unvisited vertices.
-// Top-down turns bottom-up when m_f * alpha > m_u; bottom-up turns top-down
-// when the frontier is below n / beta and shrinking.
-__global__ void direction_kernel(DirArgs a) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const unsigned long long nf = a.ctl[0], mf = a.ctl[1];
-    DirState s = *a.st;
-    s.vdeg += mf;
-    const double mu = (double)a.nnz - (double)s.vdeg;
-    int32_t next = s.cur;
-    if (a.force >= 0) {
-        next = a.force;
-    } else if (s.cur == kDirTD) {
-        if (a.alpha > 0.f && (double)mf * (double)a.alpha > mu) next = kDirBU;
-    } else if ((double)nf * (double)a.beta < (double)a.n && nf < s.prev) {
-        next = kDirTD;
+    __shared__ unsigned long long red[2][kUpdThreads / 64];
+    __shared__ bool last;
+    const int w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = cnt;
+        red[1][w] = dsum;
     }
-    s.prev = nf;
-    s.cur = next;
-    *a.st = s;
-    *a.rec = next;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s0 = 0, s1 = 0;
+        for (int k = 0; k < kUpdThreads / 64; ++k) {
+            s0 += red[0][k];
+            s1 += red[1][k];
+        }
+        __hip_atomic_store(&a.part[2 * blockIdx.x], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.part[2 * blockIdx.x + 1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    unsigned long long s0 = 0, s1 = 0;
+    for (int64_t b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+        s0 += __hip_atomic_load(&a.part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s1 += __hip_atomic_load(&a.part[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int dd = 32; dd > 0; dd >>= 1) {
+        s0 += (unsigned long long)shfl64((int64_t)s0, lane ^ dd);
+        s1 += (unsigned long long)shfl64((int64_t)s1, lane ^ dd);
+    }
+    __syncthreads();
+    if (lane == 0) {
+        red[0][w] = s0;
+        red[1][w] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long nf = 0, mf = 0;
+        for (int k = 0; k < kUpdThreads / 64; ++k) {
+            nf += red[0][k];
+            mf += red[1][k];
+        }
+        a.total[0] = nf;
+        a.total[1] = mf;
+        choose_direction(a.dir, nf, mf);
+        *a.ticket = 0;
+    }
 }
 
 // Vertices with at least one adjacency entry, one bit each.
@@ -648,6 +718,8 @@ struct csbfs_engine {
     std::vector<hipEvent_t> events;
     int32_t last_levels = 0;
     uint64_t *live = nullptr;    // [n / 64]: vertices with adjacency entries
+    unsigned long long *upd_part = nullptr;  // [kUpdMaxBlocks][2]
+    uint32_t *upd_ticket = nullptr;
     DirState *dstate = nullptr;
     // Beamer's parameters of the per-level direction choice, measured best
     // on R-MAT graphs of scale 22 (4 x 4) and 26 (8 x 8)
@@ -731,6 +803,8 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     ALLOC(e->qoff, sizeof(int64_t) * (P + 1));
     ALLOC(e->status, sizeof(int32_t));
     ALLOC(e->live, sizeof(uint64_t) * words);
+    ALLOC(e->upd_part, sizeof(unsigned long long) * 2 * kUpdMaxBlocks);
+    ALLOC(e->upd_ticket, sizeof(uint32_t));
     ALLOC(e->dstate, sizeof(DirState));
     const int64_t slots = (int64_t)max_levels + 1;
     const size_t cnt_bytes = sizeof(unsigned long long) * slots * (2 + P + 1 + 1 + e->S + P) +
@@ -854,6 +928,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     CSBFS_HIP(hipMemsetAsync(e->counters_mem, 0, e->counters_bytes, st));
     CSBFS_HIP(hipMemsetAsync(e->status, 0, sizeof(int32_t), st));
     CSBFS_HIP(hipMemsetAsync(e->ctrs, 0, sizeof(uint32_t) * P, st));
+    CSBFS_HIP(hipMemsetAsync(e->upd_ticket, 0, sizeof(uint32_t), st));
     SeedArgs sa{level, parent, e->pi, e->seen, e->view, n, words, view_words};
     const int64_t fill_items = n > view_words ? n : view_words;
     hipLaunchKernelGGL(seed_fill_kernel, dim3(grid_for(fill_items, 256, 8192)), dim3(256), 0, st, sa);
@@ -900,7 +975,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     const unsigned exp_grid = 2048, big_grid = 2048;
     const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
     const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 2048);
-    const unsigned upd_grid = grid_for((words + kUpdWords - 1) / kUpdWords, kUpdThreads / 64, 2048);
+    const unsigned upd_grid = grid_for((words + kUpdWords - 1) / kUpdWords, kUpdThreads / 64, kUpdMaxBlocks);
     DirArgs da{};
     da.st = e->dstate;
     da.n = n;
@@ -963,31 +1038,33 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
             CSBFS_HIP(hipGetLastError());
             hipLaunchKernelGGL(pull_kernel<false>, dim3(pull_grid), dim3(kPullThreads), 0, st, pa);
             CSBFS_HIP(hipGetLastError());
+        } else if (td_only) {
+            hipLaunchKernelGGL(expand_kernel<false>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
+            CSBFS_HIP(hipGetLastError());
+            hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
+            CSBFS_HIP(hipGetLastError());
         } else {
-            // the kernels of the direction not chosen for this level return at once
-            if (!bu_only) {
-                hipLaunchKernelGGL(expand_kernel<false>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
+            pb.edges = e->lc.edges + sj;
+            pb.pulled = e->lc.pulled + sj;
+            if (bu_only) {
+                hipLaunchKernelGGL(pull_kernel<true>, dim3(bu_grid), dim3(kPullThreads), 0, st, pb);
+                CSBFS_HIP(hipGetLastError());
+            } else {
+                // one launch: the push or the pull, as the level's direction
+                // says; the long-row pass returns at once on bottom-up levels
+                hipLaunchKernelGGL(level_kernel, dim3(exp_grid), dim3(kExpThreads), 0, st, ea, pb);
                 CSBFS_HIP(hipGetLastError());
                 hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
-                CSBFS_HIP(hipGetLastError());
-            }
-            if (!td_only) {
-                pb.edges = e->lc.edges + sj;
-                pb.pulled = e->lc.pulled + sj;
-                hipLaunchKernelGGL(pull_kernel<true>, dim3(bu_grid), dim3(kPullThreads), 0, st, pb);
                 CSBFS_HIP(hipGetLastError());
             }
         }
         if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
         // a2: mask, visit, f^{j+1}; a3: reduction of |f^{j+1}| and of its
-        // adjacency entries; then the direction of level j + 1
-        UpdateArgs ua{e->seen, e->pi, e->f, e->view, level, (int32_t)(j + 1), words, W,
-                      (int32_t)P, e->lc.ctl + 2 * sn, e->ctrs, g->deg};
-        hipLaunchKernelGGL(update_kernel, dim3(upd_grid), dim3(kUpdThreads), 0, st, ua);
-        CSBFS_HIP(hipGetLastError());
-        da.ctl = e->lc.ctl + 2 * sn;
+        // adjacency entries; then (last workgroup) the direction of level j + 1
         da.rec = e->lc.dir + sn;
-        hipLaunchKernelGGL(direction_kernel, dim3(1), dim3(64), 0, st, da);
+        UpdateArgs ua{e->seen, e->pi, e->f, e->view, level, (int32_t)(j + 1), words, W, (int32_t)P,
+                      e->lc.ctl + 2 * sn, e->ctrs, g->deg, e->upd_part, e->upd_ticket, da};
+        hipLaunchKernelGGL(update_kernel, dim3(upd_grid), dim3(kUpdThreads), 0, st, ua);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
         const int hs = (int)((j + 1) & 1);
