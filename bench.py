@@ -470,7 +470,7 @@ def main():
         "levels_by_direction": dir_count,
         "mode_switch": mode_switch,
         "roofline": {"bound": "hbm",
-                     "kernel": "expansion step (expand_kernel + expand_big_kernel, or pull_kernel<bottom-up>)",
+                     "kernel": "expansion step (level_kernel: top-down push or bottom-up pull; expand_big_kernel)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": traffic,
