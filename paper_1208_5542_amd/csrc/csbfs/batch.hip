@@ -602,6 +602,9 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
             wb.n_words = e->words + sj * e->Smax;
             wb.stat_sieved_bits = e->sbits + sj * e->Smax;
             wb.stat_unsieved_words = e->uwords + sj * Bm * P;
+            // roots whose level-j frontier is empty send nothing (the counter
+            // slot past max_levels is reset before this encode: no skipping)
+            wb.plane_count = j < e->L ? e->rootc + sj * Bm : nullptr;
             int r2 = launch_wah_encode(wb, st);
             if (r2) return r2;
             if (evp) CSBFS_HIP(hipEventRecord(evp[3], st));

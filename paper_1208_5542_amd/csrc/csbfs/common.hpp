@@ -86,6 +86,9 @@ struct WahBatch {
     // optional statistics (device, nullable)
     unsigned long long *stat_sieved_bits;    // [S]
     unsigned long long *stat_unsieved_words; // [planes * P]: words of WAH(piece_i), no mask
+    // optional (device, nullable): frontier size of each plane; the streams
+    // of a plane whose frontier is empty get 0 words and decode nothing
+    const unsigned long long *plane_count;   // [planes]
 };
 
 // Stream s of a batch: plane r, sender i, receiver j.

@@ -196,11 +196,20 @@ __device__ __forceinline__ void classify(const uint64_t *arr, const SegGeom &g, 
     }
 }
 
+// A plane whose frontier is empty sends no message (batched searches).
+__device__ __forceinline__ bool plane_skipped(const WahBatch &b, int64_t s) {
+    return b.plane_count && b.plane_count[s / ((int64_t)b.P * b.P)] == 0;
+}
+
 __global__ __launch_bounds__(kEncThreads) void wah_enc_count(WahBatch b) {
     __shared__ uint64_t sw[kEncLds];
     __shared__ uint64_t su[kEncLds];
     const int64_t seg = blockIdx.x;
     const int64_t s = blockIdx.y;
+    if (plane_skipped(b, s)) {
+        if (seg == 0 && threadIdx.x == 0) b.n_words[s] = 0;
+        return;
+    }
     const StreamIdx x = stream_idx(s, b.P);
     const int64_t i = x.i, j = x.j;
     const bool unsieved = b.stat_unsieved_words && i == j;
@@ -239,6 +248,7 @@ __global__ __launch_bounds__(kEncThreads) void wah_enc_emit(WahBatch b) {
     __shared__ int starts[kEncSeg + 1];
     const int64_t seg = blockIdx.x;
     const int64_t s = blockIdx.y;
+    if (plane_skipped(b, s)) return;
     const SegGeom g = seg_geom(b, seg);
 
     // Output offset and the first word-starting group after this segment.
@@ -340,6 +350,7 @@ __device__ void fill_ones(uint64_t *dst, int64_t lo, int64_t hi) {
 __global__ __launch_bounds__(kDecThreads) void wah_dec_count(WahBatch b) {
     const int64_t c = blockIdx.x;
     const int64_t s = blockIdx.y;
+    if (plane_skipped(b, s)) return;
     const int64_t G = b.nbits / kGroupBits;
     const int64_t r = b.nbits - G * kGroupBits;
     const int64_t nw = stream_words(b, s);
@@ -366,6 +377,7 @@ __global__ __launch_bounds__(kDecThreads) void wah_dec_count(WahBatch b) {
 __global__ __launch_bounds__(kDecThreads) void wah_dec_scatter(WahBatch b) {
     const int64_t c = blockIdx.x;
     const int64_t s = blockIdx.y;
+    if (plane_skipped(b, s)) return;
     const StreamIdx si = stream_idx(s, b.P);
     const int64_t i = si.i, j = si.j;
     const int64_t G = b.nbits / kGroupBits;
