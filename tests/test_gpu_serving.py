@@ -150,3 +150,48 @@ def test_serving_errors(pool):
     assert info["status"] == 0 and info["n_levels"] >= 2
     s.drain()
     s.close()
+
+
+def test_concurrent_submitters_and_eviction(pool):
+    """Four client threads submit at once to four slots whose budget holds
+    two engines for four graphs, so engines are released and rebuilt while
+    batches run; every result must still equal the single-root engine's."""
+    import threading
+
+    from paper_1208_5542_amd import csbfs
+    lib = csbfs.lib()
+    need = sorted(lib.csbfs_batch_engine_bytes(e["g"].handle, 16, 64, 0) + 4 * 16 * e["n"] for e in pool)
+    budget = need[-1] + need[-2]
+    server = csbfs.Server(slots=4, max_batch=16, max_levels=64, hbm_budget=budget)
+    gids = [server.add_graph(e["g"]) for e in pool]
+    results = {}
+    errors = []
+
+    def client(seed):
+        try:
+            reqs = _requests(pool, 40, seed)
+            outs, ids = [], []
+            for gi, root in reqs:
+                out = torch.empty(pool[gi]["n"], dtype=torch.int32, device="cuda")
+                ids.append(server.submit(gids[gi], root, out))
+                outs.append(out)
+            infos = [server.wait(i) for i in ids]
+            results[seed] = (reqs, outs, infos)
+        except Exception as exc:  # surfaced below
+            errors.append(exc)
+
+    log("serving: 4 client threads, budget of two engines")
+    threads = [threading.Thread(target=client, args=(100 + k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=240)
+    assert not errors, errors
+    assert len(results) == 4
+    assert server.bytes_held() <= budget
+    engines = [csbfs.Engine(e["g"], max_levels=64) for e in pool]
+    for reqs, outs, infos in results.values():
+        assert all(i["status"] == 0 for i in infos)
+        for (gi, root), o in zip(reqs, outs):
+            assert torch.equal(o, engines[gi].bfs(root).level)
+    server.close()
