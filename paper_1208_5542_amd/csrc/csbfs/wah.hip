@@ -347,6 +347,34 @@ __device__ void fill_ones(uint64_t *dst, int64_t lo, int64_t hi) {
     }
 }
 
+// The same two helpers on a workgroup's LDS copy of a range of words.
+constexpr int kDecLdsWords = 2048;
+
+__device__ __forceinline__ void or_bits_lds(unsigned long long *buf, int64_t bit, uint64_t v, int nbits) {
+    const int64_t q = bit >> 6;
+    const int sh = (int)(bit & 63);
+    const uint64_t lo = v << sh;
+    if (lo) atomicOr(&buf[q], (unsigned long long)lo);
+    if (sh + nbits > 64) {
+        const uint64_t hi = v >> (64 - sh);
+        if (hi) atomicOr(&buf[q + 1], (unsigned long long)hi);
+    }
+}
+
+__device__ void fill_ones_lds(unsigned long long *buf, int64_t lo, int64_t hi) {
+    int64_t q0 = lo >> 6, q1 = (hi - 1) >> 6;
+    for (int64_t q = q0; q <= q1; ++q) {
+        const int64_t a = lo > q * 64 ? lo - q * 64 : 0;
+        const int64_t e = hi < q * 64 + 64 ? hi - q * 64 : 64;
+        if (a == 0 && e == 64) {
+            buf[q] = ~0ull;  // a whole word inside one fill has no other writer
+        } else {
+            const uint64_t m = (e == 64 ? ~0ull : ((1ull << e) - 1)) & ~((1ull << a) - 1);
+            atomicOr(&buf[q], (unsigned long long)m);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kDecThreads) void wah_dec_count(WahBatch b) {
     const int64_t c = blockIdx.x;
     const int64_t s = blockIdx.y;
@@ -423,6 +451,22 @@ __global__ __launch_bounds__(kDecThreads) void wah_dec_scatter(WahBatch b) {
     }
     long long chunk_total;
     long long x = before + block_excl_scan64(mine, &chunk_total);
+
+    // The chunk's groups [g0, g1) fill output words [q0, q1]. When those fit
+    // in LDS (always for literal words: 1024 groups span 1008 words) the
+    // chunk is assembled there and written with one store per word; only
+    // the two end words, which neighbouring chunks also touch, need global
+    // atomics. Chunks whose fills span more words OR straight into dst.
+    __shared__ unsigned long long lbuf[kDecLdsWords];
+    const long long g0 = before, g1 = before + chunk_total;
+    const int64_t q0 = (g0 * kGroupBits) >> 6;
+    const int64_t q1 = g1 > g0 ? (g1 * kGroupBits - 1) >> 6 : q0;
+    const bool staged = g1 > g0 && g1 <= G && q1 - q0 + 1 <= kDecLdsWords;
+    if (staged) {
+        for (int64_t k = threadIdx.x; k <= q1 - q0; k += blockDim.x) lbuf[k] = 0;
+        __syncthreads();
+    }
+    const int64_t base_bit = q0 * 64;
     bool bad = false;
     for (int k = 0; k < kDecWpt; ++k) {
         const int64_t w = wa + k;
@@ -433,14 +477,34 @@ __global__ __launch_bounds__(kDecThreads) void wah_dec_scatter(WahBatch b) {
         }
         if (!(v[k] & kFillFlag)) {
             const uint64_t bits = __builtin_bitreverse64(v[k]) >> 1;
-            if (bits) or_bits(dst, x * kGroupBits, bits, kGroupBits);
+            if (bits) {
+                if (staged)
+                    or_bits_lds(lbuf, x * kGroupBits - base_bit, bits, kGroupBits);
+                else
+                    or_bits(dst, x * kGroupBits, bits, kGroupBits);
+            }
         } else if (v[k] & kFillBit) {
-            fill_ones(dst, x * kGroupBits, (x + g[k]) * kGroupBits);
+            if (staged)
+                fill_ones_lds(lbuf, x * kGroupBits - base_bit, (x + g[k]) * kGroupBits - base_bit);
+            else
+                fill_ones(dst, x * kGroupBits, (x + g[k]) * kGroupBits);
         }
         x += g[k];
         if (w == nreg - 1 && x != G) bad = true;
     }
     if (bad) *b.status = 1;
+    if (staged) {
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k <= q1 - q0; k += blockDim.x) {
+            const unsigned long long val = lbuf[k];
+            if (!val) continue;
+            const int64_t q = q0 + k;
+            if (q == q0 || q == q1)
+                atomicOr((unsigned long long *)&dst[q], val);
+            else
+                dst[q] |= val;  // no other workgroup writes an inner word
+        }
+    }
 }
 
 }  // namespace
