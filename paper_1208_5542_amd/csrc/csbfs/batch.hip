@@ -59,6 +59,8 @@ struct BArgs {
     int32_t P;
     unsigned long long *edges;
     int32_t *status;
+    // nullable: |f^j| summed over the roots; 0 leaves nothing to expand
+    const unsigned long long *fcount;
 };
 
 // Push kBUnroll (target v, root mask m) pairs; loads first, then atomics.
@@ -85,6 +87,7 @@ constexpr int kBRootsPerOp = 64 / kBTile;
 
 __global__ __launch_bounds__(kBThreads) void bexpand_kernel(BArgs a) {
     __shared__ uint64_t tile[kBThreads / 64][kBTile][kMaxRoots];
+    if (a.fcount && *a.fcount == 0) return;
     const int lane = threadIdx.x & 63;
     uint64_t(*tw)[kMaxRoots] = tile[threadIdx.x >> 6];
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -190,6 +193,7 @@ __global__ __launch_bounds__(kBThreads) void bexpand_kernel(BArgs a) {
 }
 
 __global__ __launch_bounds__(kBThreads) void bexpand_big_kernel(BArgs a) {
+    if (a.fcount && *a.fcount == 0) return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -237,6 +241,7 @@ struct BUpdateArgs {
     unsigned long long *total;       // [1]
     uint32_t *queue_count;           // [P], cleared for the next level
     int32_t P;
+    const unsigned long long *fcount;  // as in BArgs: 0 visits nothing
 };
 
 __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
@@ -244,6 +249,7 @@ __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
     __shared__ unsigned long long cnt[kMaxRoots];
     const int lane = threadIdx.x & 63;
     uint64_t(*tw)[kMaxRoots] = tile[threadIdx.x >> 6];
+    if (a.fcount && *a.fcount == 0) return;
     if (threadIdx.x < kMaxRoots) cnt[threadIdx.x] = 0;
     if (blockIdx.x == 0)
         for (int q = threadIdx.x; q < a.P; q += blockDim.x) a.queue_count[q] = 0;
@@ -613,14 +619,17 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
             if (evp) CSBFS_HIP(hipEventRecord(evp[4], st));
         }
         if (ev) CSBFS_HIP(hipEventRecord(ev[0], st));
+        // the iteration after the last level (one of look-ahead) does nothing
+        const unsigned long long *fc = j < e->L ? e->ctl + sj : nullptr;
         ea.edges = e->edges + sj;
+        ea.fcount = fc;
         hipLaunchKernelGGL(bexpand_kernel, dim3(grid), dim3(kBThreads), 0, st, ea);
         CSBFS_HIP(hipGetLastError());
         hipLaunchKernelGGL(bexpand_big_kernel, dim3(grid), dim3(kBThreads), 0, st, ea);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
         BUpdateArgs ua{e->vn, e->f, level, (int32_t)(j + 1), (int32_t)B, n,
-                       e->rootc + sn * Bm, e->ctl + sn, e->qcount, (int32_t)P};
+                       e->rootc + sn * Bm, e->ctl + sn, e->qcount, (int32_t)P, fc};
         hipLaunchKernelGGL(bupdate_kernel, dim3(grid_for((words + kBTile - 1) / kBTile, kBThreads / 64, 2048)), dim3(kBThreads), 0, st, ua);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));

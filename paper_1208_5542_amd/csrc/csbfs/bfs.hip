@@ -49,6 +49,9 @@ constexpr int kEvPerLevel = 5;
 constexpr int kPullTileDense = 64;  // bitmap words per wave tile of the dense pull
 constexpr int kPullTileBU = 4;      // ... and of the bottom-up pull (many more candidates)
 constexpr int32_t kDirTD = CSBFS_DIR_TOP_DOWN, kDirBU = CSBFS_DIR_BOTTOM_UP, kDirDense = CSBFS_DIR_DENSE;
+// No frontier left: every kernel of the iteration returns at once (the
+// host learns of it one iteration late, and that iteration costs nothing).
+constexpr int32_t kDirIdle = 3;
 
 struct BigItem {
     int32_t block;
@@ -234,7 +237,8 @@ __device__ __forceinline__ void expand_body(const ExpandArgs &a) {
 
 template <bool kDense>
 __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
-    if (*a.dir == kDirBU) return;
+    const int32_t d = *a.dir;
+    if (d == kDirBU || d == kDirIdle) return;
     expand_body<kDense>(a);
 }
 
@@ -242,7 +246,8 @@ __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
 // processor, strided over the grid.
 template <bool kDense>
 __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
-    if (*a.dir == kDirBU) return;
+    const int32_t d = *a.dir;
+    if (d == kDirBU || d == kDirIdle) return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -444,7 +449,8 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
 
 template <bool kBottomUp>
 __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
-    if (kBottomUp && *a.dir != kDirBU) return;
+    const int32_t d = *a.dir;
+    if (kBottomUp ? d != kDirBU : d == kDirIdle) return;
     pull_body<kBottomUp>(a);
 }
 
@@ -452,9 +458,10 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
 // top-down push or the bottom-up pull, as the level's direction says.
 static_assert(kExpThreads == kPullThreads, "one block size for both directions");
 __global__ __launch_bounds__(kExpThreads) void level_kernel(ExpandArgs ea, PullArgs pa) {
-    if (*ea.dir == kDirBU)
+    const int32_t d = *ea.dir;
+    if (d == kDirBU)
         pull_body<true>(pa);
-    else
+    else if (d != kDirIdle)
         expand_body<false>(ea);
 }
 
@@ -463,7 +470,7 @@ struct DirState {
     int32_t cur;              // direction of the level expanded next
     int32_t pad;
     unsigned long long vdeg;  // adjacency entries of the visited vertices
-    unsigned long long prev;  // size of the frontier before the newest one
+    unsigned long long prev;  // size of the newest frontier (compared with the next one)
 };
 
 struct DirArgs {
@@ -485,7 +492,9 @@ __device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsign
     s.vdeg += mf;
     const double mu = (double)a.nnz - (double)s.vdeg;
     int32_t next = s.cur;
-    if (a.force >= 0) {
+    if (nf == 0) {
+        next = kDirIdle;
+    } else if (a.force >= 0) {
         next = a.force;
     } else if (s.cur == kDirTD) {
         if (a.alpha > 0.f && (double)mf * (double)a.alpha > mu) next = kDirBU;
@@ -527,6 +536,9 @@ constexpr int kUpdMaxBlocks = 512;  // workgroups of the update (their sums meet
 // its sums; the last one to finish adds them up, stores the level's
 // counters and chooses the next level's direction.
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
+    // An empty frontier visits nothing. No workgroup reads the state after
+    // the last one rewrites it: that one runs after every ticket is taken.
+    if (a.dir.st->cur == kDirIdle) return;
     const int lane = threadIdx.x & 63;
     if (blockIdx.x == 0 && threadIdx.x < a.P) a.ctrs[threadIdx.x] = 0;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -998,6 +1010,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     wb.nchunk = e->nchunk;
     wb.dst_base = e->view;
     wb.status = e->status;
+    wb.plane_count = &e->dstate->prev;  // |f^j| in iteration j: no message once it is 0
 
     // Iteration j: the messages carrying f^j (j >= 1: sieve + compress, then
     // decode into the views), the expansion of f^j, the update producing
@@ -1075,9 +1088,9 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     };
 
     // The host reads |f^{k+1}| while iteration k + 1 already runs on the GPU
-    // (one level of look-ahead). When f^{k+1} turns out empty, that iteration
-    // ran on empty views and an empty frontier: it changed no output, and its
-    // counters lie past the last reported level.
+    // (one level of look-ahead). When f^{k+1} turns out empty, the update
+    // that found it chose the idle direction: every kernel of that iteration
+    // returned at once, and its counters lie past the last reported level.
     unsigned long long known = 1;  // |f^0|
     rc = enqueue_iter(0, known);
     if (rc) return rc;
