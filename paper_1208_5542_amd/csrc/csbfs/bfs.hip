@@ -42,7 +42,7 @@ namespace csbfs {
 namespace {
 
 constexpr int kExpThreads = 256;
-constexpr int kUpdThreads = 256;
+constexpr int kUpdThreads = 1024;
 constexpr int kPullThreads = 256;
 constexpr int kPullRounds = 16;  // per-lane steps (kUnroll entries each) before the wave helps
 constexpr int kEvPerLevel = 5;
@@ -526,7 +526,10 @@ struct UpdateArgs {
 };
 
 constexpr int kUpdWords = 16;     // bitmap words per wavefront step of the update
-constexpr int kUpdMaxBlocks = 512;  // workgroups of the update (their sums meet in one)
+// Workgroups of the update (their sums meet in one): one per CU. Each
+// workgroup's release of its sums writes back its XCD's L2, so the update
+// uses few large workgroups rather than many small ones.
+constexpr int kUpdMaxBlocks = 256;
 
 // A wavefront takes kUpdWords consecutive bitmap words at a time: lane k
 // (< kUpdWords) handles word q0 + k (t = S & ~pi, pi = S, f = t); the wave
@@ -563,18 +566,16 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
                 a.view[(i * a.P + j) * a.W + ql] = 0;
             }
         }
+        // all the masked loads of the step are in flight before any is summed
         int32_t d[kUpdWords];
 #pragma unroll
         for (int k = 0; k < kUpdWords; ++k) {
             d[k] = 0;
-            const uint64_t t = (uint64_t)shfl64((int64_t)tk, k);
-            if (t) {
+            const uint64_t t = readlane64(tk, k);
+            if ((t >> lane) & 1) {
                 const int64_t v = ((q0 + k) << 6) + lane;
-                const int32_t dv = a.deg[v];
-                if ((t >> lane) & 1) {
-                    a.level[v] = a.next_level;
-                    d[k] = dv;
-                }
+                d[k] = a.deg[v];
+                a.level[v] = a.next_level;
             }
         }
 #pragma unroll

@@ -72,6 +72,13 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
     return ((int64_t)hi << 32) | (uint32_t)lo;
 }
 
+// Lane src of v (src wave-uniform) as a scalar, whatever the exec mask.
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) v |= (uint64_t)shfl64((int64_t)v, (threadIdx.x & 63) ^ d);
