@@ -351,7 +351,9 @@ struct csbfs_batch_engine {
     uint32_t flags = 0;
     int64_t cap = 0, nseg = 0, nchunk = 0, Smax = 0;
     uint64_t *vn = nullptr, *f = nullptr, *view = nullptr, *arena = nullptr;
-    int32_t *seg_count = nullptr, *seg_first = nullptr;
+    unsigned long long *look = nullptr;  // encoder look-back words [Smax * nseg]
+    uint32_t *enc_ticket = nullptr;      // [kTicketStride * Smax], after look
+    size_t look_bytes = 0;
     int64_t *chunk_groups = nullptr;
     BItem *queue = nullptr;
     int64_t *qoff = nullptr;
@@ -392,9 +394,9 @@ namespace {
 
 // Device bytes of every buffer csbfs_batch_engine_create allocates.
 struct BatchSizes {
-    int64_t vis, nx, f, view, arena, seg, chunk, queue, qoff, qcount, roots, status, counters;
+    int64_t vis, nx, f, view, arena, look, ticket, chunk, queue, qoff, qcount, roots, status, counters;
     int64_t total() const {
-        return vis + nx + f + view + arena + 2 * seg + chunk + queue + qoff + qcount + roots + status + counters;
+        return vis + nx + f + view + arena + look + ticket + chunk + queue + qoff + qcount + roots + status + counters;
     }
 };
 
@@ -410,7 +412,8 @@ BatchSizes batch_sizes(const csbfs_graph *g, int64_t B, int64_t L, uint32_t flag
     z.f = 8 * B * (n / 64);
     z.view = 8 * B * P * (n / 64);
     z.arena = 8 * Smax * wah_cap(g->R) * arena_slots;
-    z.seg = 4 * Smax * enc_segments(g->R);
+    z.look = 8 * Smax * enc_segments(g->R);
+    z.ticket = 4 * kTicketStride * Smax;
     z.chunk = 8 * Smax * dec_chunks(g->R);
     z.queue = (int64_t)sizeof(BItem) * (items > 0 ? items : 1);
     z.qoff = 8 * (P + 1);
@@ -476,8 +479,9 @@ extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots
     BALLOC(e->f, z.f);
     BALLOC(e->view, z.view);
     BALLOC(e->arena, z.arena);
-    BALLOC(e->seg_count, z.seg);
-    BALLOC(e->seg_first, z.seg);
+    // encoder look-back words, then its tickets: zero before the first encode
+    BALLOC(e->look, z.look + z.ticket);
+    e->enc_ticket = reinterpret_cast<uint32_t *>(e->look + e->Smax * e->nseg);
     BALLOC(e->chunk_groups, z.chunk);
     BALLOC(e->queue, z.queue);
     BALLOC(e->qoff, z.qoff);
@@ -488,6 +492,12 @@ extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots
     BALLOC(e->counters_mem, cnt_bytes);
 #undef BALLOC
     e->counters_bytes = cnt_bytes;
+    e->look_bytes = (size_t)(z.look + z.ticket);
+    const hipError_t zerr = hipMemset(e->look, 0, e->look_bytes);
+    if (zerr != hipSuccess) {
+        bengine_release(e);
+        return hip_fail(zerr, "hipMemset(look)", __FILE__, __LINE__);
+    }
     unsigned long long *c = (unsigned long long *)e->counters_mem;
     e->ctl = c;
     c += slots;
@@ -582,11 +592,12 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
     wb.planes = (int32_t)B;
     wb.bits_plane_stride = words;
     wb.dst_plane_stride = vplane;
-    wb.seg_count = e->seg_count;
-    wb.seg_first = e->seg_first;
+    wb.look = e->look;
+    wb.ticket = e->enc_ticket;
     wb.nseg = e->nseg;
     wb.chunk_groups = e->chunk_groups;
     wb.nchunk = e->nchunk;
+    wb.chunk_starts = 1;  // the decode reads the chunk starts the encode records
     wb.dst_base = e->view;
     wb.status = e->status;
 
@@ -675,6 +686,9 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
     }
     CSBFS_HIP(hipStreamSynchronize(st));
     if (hstatus != 0) {
+        // an encode that gave up waiting may have left look-back state behind
+        CSBFS_HIP(hipMemsetAsync(e->look, 0, e->look_bytes, st));
+        CSBFS_HIP(hipStreamSynchronize(st));
         if (hstatus == 1) return fail(CSBFS_ECORRUPT, "csbfs_batch_bfs: a stream failed validation while decoding");
         return fail(CSBFS_ECORRUPT, "csbfs_batch_bfs: internal consistency check failed");
     }

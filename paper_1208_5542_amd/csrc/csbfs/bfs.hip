@@ -716,7 +716,9 @@ struct csbfs_engine {
     uint32_t flags = 0;
     int64_t S = 0, cap = 0, nseg = 0, nchunk = 0;
     uint64_t *pi = nullptr, *f = nullptr, *seen = nullptr, *view = nullptr, *arena = nullptr;
-    int32_t *seg_count = nullptr, *seg_first = nullptr;
+    unsigned long long *look = nullptr;  // encoder look-back words [S * nseg]
+    uint32_t *enc_ticket = nullptr;      // [kTicketStride * S], after look
+    size_t look_bytes = 0;
     int64_t *chunk_groups = nullptr;
     BigItem *queue = nullptr;
     uint32_t *ctrs = nullptr;     // [P]: chunk-queue items pushed
@@ -808,8 +810,10 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     ALLOC(e->seen, sizeof(uint64_t) * words);
     ALLOC(e->view, sizeof(uint64_t) * P * words);
     ALLOC(e->arena, sizeof(uint64_t) * e->S * e->cap * arena_slots);
-    ALLOC(e->seg_count, sizeof(int32_t) * e->S * e->nseg);
-    ALLOC(e->seg_first, sizeof(int32_t) * e->S * e->nseg);
+    // encoder look-back words, then its tickets: zero before the first encode
+    e->look_bytes = sizeof(unsigned long long) * e->S * e->nseg + sizeof(uint32_t) * kTicketStride * e->S;
+    ALLOC(e->look, e->look_bytes);
+    e->enc_ticket = reinterpret_cast<uint32_t *>(e->look + e->S * e->nseg);
     ALLOC(e->chunk_groups, sizeof(int64_t) * e->S * e->nchunk);
     ALLOC(e->queue, sizeof(BigItem) * e->queue_cap);
     ALLOC(e->ctrs, sizeof(uint32_t) * P);
@@ -825,6 +829,11 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     ALLOC(e->counters_mem, cnt_bytes);
 #undef ALLOC
     e->counters_bytes = cnt_bytes;
+    const hipError_t zerr = hipMemset(e->look, 0, e->look_bytes);
+    if (zerr != hipSuccess) {
+        engine_release(e);
+        return hip_fail(zerr, "hipMemset(look)", __FILE__, __LINE__);
+    }
     unsigned long long *c = (unsigned long long *)e->counters_mem;
     e->lc.ctl = c;
     c += slots * 2;
@@ -1004,11 +1013,12 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     wb.words_per_piece = W;
     wb.cap = e->cap;
     wb.P = (int32_t)P;
-    wb.seg_count = e->seg_count;
-    wb.seg_first = e->seg_first;
+    wb.look = e->look;
+    wb.ticket = e->enc_ticket;
     wb.nseg = e->nseg;
     wb.chunk_groups = e->chunk_groups;
     wb.nchunk = e->nchunk;
+    wb.chunk_starts = 1;  // the decode reads the chunk starts the encode records
     wb.dst_base = e->view;
     wb.status = e->status;
     wb.plane_count = &e->dstate->prev;  // |f^j| in iteration j: no message once it is 0
@@ -1141,6 +1151,9 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     }
     CSBFS_HIP(hipStreamSynchronize(st));
     if (hstatus != 0) {
+        // an encode that gave up waiting may have left look-back state behind
+        CSBFS_HIP(hipMemsetAsync(e->look, 0, e->look_bytes, st));
+        CSBFS_HIP(hipStreamSynchronize(st));
         if (hstatus == 1) return fail(CSBFS_ECORRUPT, "csbfs_bfs: a stream failed validation while decoding");
         return fail(CSBFS_ECORRUPT, "csbfs_bfs: internal consistency check failed");
     }

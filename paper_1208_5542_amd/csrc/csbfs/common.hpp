@@ -37,7 +37,10 @@ constexpr uint64_t kMask63 = (1ull << 63) - 1;
 
 // Encoder tiling: a workgroup of kEncThreads threads classifies one segment
 // of kEncSeg groups, kEncGpt consecutive groups per thread.
-constexpr int kEncThreads = 256;
+constexpr int kEncThreads = 512;
+// Encoder tickets of a stream: its own 128-byte line (atomics on one line
+// are serialized).
+constexpr int kTicketStride = 32;
 constexpr int kEncGpt = 4;
 constexpr int kEncSeg = kEncThreads * kEncGpt;
 // Decoder tiling: a workgroup reads one chunk of kDecChunk stream words.
@@ -74,13 +77,18 @@ struct WahBatch {
     int32_t planes;             // 0 or 1 for one search
     int64_t bits_plane_stride;
     int64_t dst_plane_stride;
-    // encoder scratch: per (stream, segment) flag counts and first flagged group
-    int32_t *seg_count;         // device [S * nseg]
-    int32_t *seg_first;         // device [S * nseg]
+    // encoder scratch, zero between launches (each launch leaves it zero):
+    // per (stream, segment) look-back words; per stream a segment ticket and
+    // a count of finished segments
+    unsigned long long *look;   // device [S * nseg]
+    uint32_t *ticket;           // device [kTicketStride * S]
     int64_t nseg;
-    // decoder scratch: per (stream, chunk) group totals
+    // decoder scratch: per (stream, chunk) group totals, or (chunk_starts)
+    // the first group of each chunk, recorded by the encoder: the decoder
+    // then runs one pass and checks that consecutive chunks meet
     int64_t *chunk_groups;      // device [S * nchunk]
     int64_t nchunk;
+    int32_t chunk_starts;
     uint64_t *dst_base;         // decoder output
     int32_t *status;            // device [1], non-zero on a corrupt stream
     // optional statistics (device, nullable)

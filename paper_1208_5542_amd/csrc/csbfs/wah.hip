@@ -4,22 +4,25 @@
 // Encoder. Group x of a piece is bits [63x, 63x + 63). A group is Z (all 0),
 // O (all 1) or L (mixed). Group x starts a word iff it is L, or x = 0, or its
 // class differs from group x - 1's; a run-starting fill group x covers the
-// groups up to the next word-starting group. Pass 1 (wah_enc_count) counts
-// word-starting groups per segment of kEncSeg groups and records the first
-// one; pass 2 (wah_enc_emit) turns the counts of earlier segments into the
-// segment's output offset, ranks the word-starting groups with a block scan,
-// and writes every word, reading the end of a trailing run from the first
-// word-starting group of the later segments. The sieve (AND with the
+// groups up to the next word-starting group. One pass (wah_encode_kernel):
+// a workgroup per segment of kEncSeg groups ranks the segment's
+// word-starting groups with a block scan, finds the count of those before
+// the segment by a decoupled look-back over the earlier segments' published
+// counts, and writes its words; a fill that runs past the segment's end is written by the
+// segment where the run ends. The sieve (AND with the
 // directory vector) is applied while the segment is staged into LDS, so the
 // sieved piece is never written to memory.
 //
-// Decoder. Pass 1 (wah_dec_count) sums the groups each chunk of kDecChunk
-// words covers; pass 2 (wah_dec_scatter) gives every word its first group by a
-// block scan plus the totals of earlier chunks, and ORs literal and 1-fill
+// Decoder. wah_dec_scatter gives every word its first group by a block scan
+// from its chunk's first group, and ORs literal and 1-fill
 // bits into the destination (0-fills write nothing: the destination starts
-// zeroed). Every stream is validated: zero-length fills, group totals that do
-// not match floor(N/63), or active-word bits above r set the status flag.
-#include "common.hpp"
+// zeroed). A chunk of kDecChunk words learns its first group from the
+// encoder, which records it while writing the chunk's first word (searches),
+// or from a first pass (wah_dec_count) that sums the groups of every chunk
+// (streams from elsewhere). Every stream is validated: zero-length fills,
+// group totals that do not match floor(N/63), chunks that do not meet, or
+// active-word bits above r set the status flag.
+#include "device.hpp"
 
 namespace csbfs {
 namespace {
@@ -201,28 +204,183 @@ __device__ __forceinline__ bool plane_skipped(const WahBatch &b, int64_t s) {
     return b.plane_count && b.plane_count[s / ((int64_t)b.P * b.P)] == 0;
 }
 
-__global__ __launch_bounds__(kEncThreads) void wah_enc_count(WahBatch b) {
+// Look-back words of the encoder, one per (stream, segment): a segment's
+// state and value sit in one 64-bit word written by one atomic store, so a
+// reader sees both or neither. State 1 holds the segment's own aggregate,
+// state 2 the inclusive prefix through it. A value is (count of word-starting
+// groups, the last of them, its class) and prefixes combine by adding the
+// counts and keeping the later last group.
+constexpr int kLbBits = 29;  // count and group-index fields: at most 2^29 - 1 groups
+constexpr uint64_t kLbField = (1ull << kLbBits) - 1;
+constexpr uint64_t kLbAgg = 1ull << 62, kLbInc = 2ull << 62;
+constexpr uint64_t kLbHasLast = 1ull << 60;
+constexpr uint64_t kLbLastMask = (kLbField << kLbBits) | (3ull << (2 * kLbBits)) | kLbHasLast;
+constexpr uint32_t kLbSpinLimit = 1u << 22;  // polls of one look-back window
+
+__device__ __forceinline__ uint64_t lb_value(int64_t cnt, int64_t last, int cls) {
+    return (uint64_t)cnt | (cnt ? ((uint64_t)last << kLbBits) | ((uint64_t)cls << (2 * kLbBits)) | kLbHasLast : 0);
+}
+
+// Exclusive prefix of segment seg (> 0) of one stream, by wave 0: windows of
+// up to 64 earlier segments are read at once, each lane waiting for its
+// segment to publish, until a window holds an inclusive prefix.
+__device__ uint64_t lb_prefix(const WahBatch &b, unsigned long long *look, int64_t seg) {
+    const int lane = threadIdx.x & 63;
+    int64_t cnt = 0;
+    uint64_t last = 0;
+    for (int64_t k0 = seg - 1;; k0 -= 64) {
+        const int64_t k = k0 - lane;
+        // lanes before segment 0 hold an empty inclusive prefix
+        uint64_t v = k >= 0 ? __hip_atomic_load(&look[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kLbInc;
+        uint32_t polls = 0;
+        while (__ballot((v >> 62) == 0)) {
+            if (++polls == kLbSpinLimit) {  // a lost publication: flag the stream, stop waiting
+                if (lane == 0 && b.status) *b.status = 1;
+                if ((v >> 62) == 0) v = kLbInc;
+                break;
+            }
+            if ((v >> 62) == 0) v = __hip_atomic_load(&look[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint64_t inc = __ballot((v >> 62) == 2);
+        const int stop = inc ? __ffsll((unsigned long long)inc) - 1 : 63;
+        long long c = lane <= stop ? (long long)(v & kLbField) : 0;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+        cnt += c;
+        const uint64_t has = __ballot(lane <= stop && (v & kLbHasLast));
+        if (!last && has) last = readlane64(v, __ffsll((unsigned long long)has) - 1) & kLbLastMask;
+        if (inc) break;
+    }
+    return (uint64_t)cnt | last;
+}
+
+// One pass per stream segment: stage, classify, publish the segment's count,
+// look back for the counts before it, write its words. The trailing fill of
+// a segment ends at a later segment's first word-starting group, so the
+// segment holding that group (or the last segment, which ends every run)
+// writes the fill word; the look-back carries its start and class. The last
+// workgroup of a stream to finish clears the stream's look-back words and
+// tickets for the next launch.
+__global__ __launch_bounds__(kEncThreads) void wah_encode_kernel(WahBatch b) {
     __shared__ uint64_t sw[kEncLds];
     __shared__ uint64_t su[kEncLds];
-    const int64_t seg = blockIdx.x;
+    __shared__ int starts[kEncSeg];
+    __shared__ int64_t sh_seg;
+    __shared__ int sh_last_cls;
+    __shared__ uint64_t sh_prefix;
+    __shared__ bool sh_reset;
     const int64_t s = blockIdx.y;
     if (plane_skipped(b, s)) {
-        if (seg == 0 && threadIdx.x == 0) b.n_words[s] = 0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) b.n_words[s] = 0;
+        return;
+    }
+    // segments in the order the workgroups start, so every awaited one runs
+    uint32_t *ticket = b.ticket + s * kTicketStride;  // [0] segments started, [1] finished
+    if (threadIdx.x == 0) sh_seg = atomicAdd(&ticket[0], 1u);
+    __syncthreads();
+    const int64_t seg = sh_seg;
+    if (seg >= b.nseg) {  // scratch not zero at launch: refuse the stream
+        if (threadIdx.x == 0 && b.status) *b.status = 1;
         return;
     }
     const StreamIdx x = stream_idx(s, b.P);
-    const int64_t i = x.i, j = x.j;
-    const bool unsieved = b.stat_unsieved_words && i == j;
+    const bool unsieved = b.stat_unsieved_words && x.i == x.j;
     const SegGeom g = seg_geom(b, seg);
     stage(b, s, g, sw, unsieved ? su : nullptr);
 
     const int64_t xa = g.x0 + (int64_t)threadIdx.x * kEncGpt;
     const int64_t xb = xa + kEncGpt < g.x1 ? xa + kEncGpt : g.x1;
-    int flags = 0, first = INT32_MAX;
+    int cls[kEncGpt];
+    uint64_t val[kEncGpt];
+    int nflag = 0;
     long long ones = 0;
-    if (xa < g.x1) classify(sw, g, xa, xb, flags, first, ones);
-    const int cnt = block_reduce(flags, SumI32(), 0);
-    const int fst = block_reduce(first, MinI32(), INT32_MAX);
+#pragma unroll
+    for (int k = 0; k < kEncGpt; ++k) cls[k] = -1;
+    if (xa < g.x1) {
+        int prev = xa > 0 ? group_class(group_bits(sw, xa - 1, g.wlo)) : -1;
+        for (int k = 0; k < kEncGpt; ++k) {
+            const int64_t gx = xa + k;
+            if (gx >= xb) break;
+            val[k] = group_bits(sw, gx, g.wlo);
+            ones += __popcll(val[k]);
+            const int c = group_class(val[k]);
+            if (c == 2 || c != prev) {
+                cls[k] = c;
+                ++nflag;
+            }
+            prev = c;
+        }
+    }
+    int seg_words = 0;
+    const int base = block_excl_scan(nflag, &seg_words);
+    {
+        int pos = base;
+        for (int k = 0; k < kEncGpt; ++k) {
+            if (cls[k] < 0) continue;
+            if (pos == seg_words - 1) sh_last_cls = cls[k];
+            starts[pos++] = (int)(xa + k);
+        }
+    }
+    __syncthreads();
+
+    unsigned long long *look = b.look + s * b.nseg;
+    if (threadIdx.x < 64) {
+        const uint64_t mine = lb_value(seg_words, seg_words ? starts[seg_words - 1] : 0, sh_last_cls);
+        if (seg == 0) {
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(&look[0], mine | kLbInc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sh_prefix = 0;
+            }
+        } else {
+            if (threadIdx.x == 0)
+                __hip_atomic_store(&look[seg], mine | kLbAgg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t pre = lb_prefix(b, look, seg);
+            if (threadIdx.x == 0) {
+                const uint64_t inc = ((pre & kLbField) + seg_words) | (seg_words ? (mine & kLbLastMask) : (pre & kLbLastMask));
+                __hip_atomic_store(&look[seg], inc | kLbInc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sh_prefix = pre;
+            }
+        }
+    }
+    __syncthreads();
+    const uint64_t pre = sh_prefix;
+    const int64_t offset = (int64_t)(pre & kLbField);
+
+    // every index is below the stream's capacity unless the look-back failed
+    uint64_t *out = b.out_base + s * b.cap;
+    int64_t *cstart = b.chunk_starts ? b.chunk_groups + s * b.nchunk : nullptr;
+    const bool fits = offset + seg_words + 1 <= b.cap;
+    int pos = base;
+    for (int k = 0; k < kEncGpt && fits; ++k) {
+        if (cls[k] < 0) continue;
+        const int64_t gx = xa + k;
+        if (cstart && (offset + pos) % kDecChunk == 0) cstart[(offset + pos) / kDecChunk] = gx;
+        if (cls[k] == 2) {
+            out[offset + pos] = __builtin_bitreverse64(val[k]) >> 1;  // bit (62 - t) = group bit t
+        } else if (pos + 1 < seg_words || g.last) {
+            const int64_t end = pos + 1 < seg_words ? starts[pos + 1] : g.G;
+            out[offset + pos] = kFillFlag | (cls[k] == 1 ? kFillBit : 0) | (uint64_t)(end - gx);
+        }
+        ++pos;
+    }
+    if (threadIdx.x == 0) {
+        if (!fits && b.status) *b.status = 1;
+        // the fill that began at the last word-starting group before this segment
+        const int prev_cls = (int)((pre >> (2 * kLbBits)) & 3);
+        if (fits && offset >= 1 && (pre & kLbHasLast) && prev_cls != 2 && (seg_words > 0 || g.last)) {
+            const int64_t begin = (int64_t)((pre >> kLbBits) & kLbField);
+            const int64_t end = seg_words > 0 ? starts[0] : g.G;
+            out[offset - 1] = kFillFlag | (prev_cls == 1 ? kFillBit : 0) | (uint64_t)(end - begin);
+            if (cstart && (offset - 1) % kDecChunk == 0) cstart[(offset - 1) / kDecChunk] = begin;
+        }
+        if (g.last) {
+            int64_t total = offset + seg_words;
+            if (g.r > 0 && fits) out[total++] = active_word(sw, g);
+            b.n_words[s] = fits ? total : 0;
+        }
+    }
+
+    // statistics: set bits after the sieve, words of the unsieved piece
     long long tot = block_reduce(ones, SumI64(), 0LL);
     int ucnt = 0;
     if (unsieved) {
@@ -232,87 +390,23 @@ __global__ __launch_bounds__(kEncThreads) void wah_enc_count(WahBatch b) {
         ucnt = block_reduce(uf, SumI32(), 0);
     }
     if (threadIdx.x == 0) {
-        b.seg_count[s * b.nseg + seg] = cnt;
-        b.seg_first[s * b.nseg + seg] = fst;
         if (g.last && g.r > 0) tot += __popcll(active_word(sw, g));
         if (b.stat_sieved_bits && tot) atomicAdd(&b.stat_sieved_bits[s], (unsigned long long)tot);
         if (unsieved) {
             const int words = ucnt + (g.last && g.r > 0 ? 1 : 0);
-            if (words) atomicAdd(&b.stat_unsieved_words[x.r * b.P + i], (unsigned long long)words);
+            if (words) atomicAdd(&b.stat_unsieved_words[x.r * b.P + x.i], (unsigned long long)words);
         }
+        // every look-back of the stream has returned once all its segments count here
+        sh_reset = atomicAdd(&ticket[1], 1u) == (uint32_t)(b.nseg - 1);
     }
-}
-
-__global__ __launch_bounds__(kEncThreads) void wah_enc_emit(WahBatch b) {
-    __shared__ uint64_t sw[kEncLds];
-    __shared__ int starts[kEncSeg + 1];
-    const int64_t seg = blockIdx.x;
-    const int64_t s = blockIdx.y;
-    if (plane_skipped(b, s)) return;
-    const SegGeom g = seg_geom(b, seg);
-
-    // Output offset and the first word-starting group after this segment.
-    int before = 0, after = INT32_MAX;
-    for (int64_t k = threadIdx.x; k < b.nseg; k += blockDim.x) {
-        if (k < seg) before += b.seg_count[s * b.nseg + k];
-        else if (k > seg) after = min(after, b.seg_first[s * b.nseg + k]);
-    }
-    const int offset = block_reduce(before, SumI32(), 0);
-    after = block_reduce(after, MinI32(), INT32_MAX);
-    const int64_t next_after = after == INT32_MAX ? g.G : after;
-
-    stage(b, s, g, sw, nullptr);
-    const int64_t xa = g.x0 + (int64_t)threadIdx.x * kEncGpt;
-    const int64_t xb = xa + kEncGpt < g.x1 ? xa + kEncGpt : g.x1;
-    int cls[kEncGpt];
-    uint64_t val[kEncGpt];
-    int nflag = 0;
-    if (xa < g.x1) {
-        int prev = xa > 0 ? group_class(group_bits(sw, xa - 1, g.wlo)) : -1;
-        for (int k = 0; k < kEncGpt; ++k) {
-            const int64_t x = xa + k;
-            cls[k] = -1;
-            if (x >= xb) continue;
-            val[k] = group_bits(sw, x, g.wlo);
-            const int c = group_class(val[k]);
-            if (c == 2 || c != prev) {
-                cls[k] = c;
-                ++nflag;
-            }
-            prev = c;
-        }
-    } else {
-        for (int k = 0; k < kEncGpt; ++k) cls[k] = -1;
-    }
-    int seg_words = 0;
-    const int base = block_excl_scan(nflag, &seg_words);
-    {
-        int pos = base;
-        for (int k = 0; k < kEncGpt; ++k)
-            if (cls[k] >= 0) starts[pos++] = (int)(xa + k);
-    }
-    if (threadIdx.x == 0) starts[seg_words] = (int)next_after;
     __syncthreads();
-
-    uint64_t *out = b.out_base + s * b.cap;
-    int pos = base;
-    for (int k = 0; k < kEncGpt; ++k) {
-        if (cls[k] < 0) continue;
-        const int64_t x = xa + k;
-        uint64_t word;
-        if (cls[k] == 2) {
-            word = __builtin_bitreverse64(val[k]) >> 1;  // bit (62 - t) = group bit t
-        } else {
-            const uint64_t c = (uint64_t)(starts[pos + 1] - x);
-            word = kFillFlag | (cls[k] == 1 ? kFillBit : 0) | c;
+    if (sh_reset) {
+        for (int64_t k = threadIdx.x; k < b.nseg; k += blockDim.x)
+            __hip_atomic_store(&look[k], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(&ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        out[offset + pos] = word;
-        ++pos;
-    }
-    if (g.last && threadIdx.x == 0) {
-        int64_t total = offset + seg_words;
-        if (g.r > 0) out[total++] = active_word(sw, g);
-        b.n_words[s] = total;
     }
 }
 
@@ -433,8 +527,16 @@ __global__ __launch_bounds__(kDecThreads) void wah_dec_scatter(WahBatch b) {
     if (nw < 0 || nw > b.cap || w0 >= nreg) return;
 
     long long before = 0;
-    for (int64_t k = threadIdx.x; k < c; k += blockDim.x) before += b.chunk_groups[s * b.nchunk + k];
-    before = block_reduce(before, SumI64(), 0LL);
+    if (b.chunk_starts) {
+        before = c > 0 ? b.chunk_groups[s * b.nchunk + c] : 0;
+        if (before < 0 || before > G) {
+            if (threadIdx.x == 0) *b.status = 1;
+            return;
+        }
+    } else {
+        for (int64_t k = threadIdx.x; k < c; k += blockDim.x) before += b.chunk_groups[s * b.nchunk + k];
+        before = block_reduce(before, SumI64(), 0LL);
+    }
 
     uint64_t v[kDecWpt];
     long long g[kDecWpt];
@@ -451,6 +553,10 @@ __global__ __launch_bounds__(kDecThreads) void wah_dec_scatter(WahBatch b) {
     }
     long long chunk_total;
     long long x = before + block_excl_scan64(mine, &chunk_total);
+    // recorded starts: this chunk must end where the next one starts
+    if (b.chunk_starts && threadIdx.x == 0 && w0 + kDecChunk < nreg &&
+        before + chunk_total != b.chunk_groups[s * b.nchunk + c + 1])
+        *b.status = 1;
 
     // The chunk's groups [g0, g1) fill output words [q0, q1]. When those fit
     // in LDS (always for literal words: 1024 groups span 1008 words) the
@@ -511,10 +617,9 @@ __global__ __launch_bounds__(kDecThreads) void wah_dec_scatter(WahBatch b) {
 
 int launch_wah_encode(const WahBatch &b, hipStream_t stream) {
     const int64_t S = batch_streams(b);
+    if (b.nbits / kGroupBits > kLbField) return fail(CSBFS_EINVAL, "WAH encode: more than 2^29 - 1 groups");
     dim3 grid((unsigned)b.nseg, (unsigned)S);
-    hipLaunchKernelGGL(wah_enc_count, grid, dim3(kEncThreads), 0, stream, b);
-    CSBFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(wah_enc_emit, grid, dim3(kEncThreads), 0, stream, b);
+    hipLaunchKernelGGL(wah_encode_kernel, grid, dim3(kEncThreads), 0, stream, b);
     CSBFS_HIP(hipGetLastError());
     return CSBFS_OK;
 }
@@ -522,8 +627,10 @@ int launch_wah_encode(const WahBatch &b, hipStream_t stream) {
 int launch_wah_decode(const WahBatch &b, hipStream_t stream) {
     const int64_t S = batch_streams(b);
     dim3 grid((unsigned)b.nchunk, (unsigned)S);
-    hipLaunchKernelGGL(wah_dec_count, grid, dim3(kDecThreads), 0, stream, b);
-    CSBFS_HIP(hipGetLastError());
+    if (!b.chunk_starts) {
+        hipLaunchKernelGGL(wah_dec_count, grid, dim3(kDecThreads), 0, stream, b);
+        CSBFS_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(wah_dec_scatter, grid, dim3(kDecThreads), 0, stream, b);
     CSBFS_HIP(hipGetLastError());
     return CSBFS_OK;
@@ -539,15 +646,15 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct WsLayout {
-    size_t seg_count, seg_first, chunk_groups, n_words, total;
+    size_t look, ticket, chunk_groups, n_words, total;
 };
 WsLayout ws_layout(int64_t nbits) {
     WsLayout l;
     const int64_t nseg = enc_segments(nbits);
     const int64_t nchunk = dec_chunks(nbits);
-    l.seg_count = 0;
-    l.seg_first = l.seg_count + align_up(sizeof(int32_t) * nseg);
-    l.chunk_groups = l.seg_first + align_up(sizeof(int32_t) * nseg);
+    l.look = 0;
+    l.ticket = l.look + align_up(sizeof(unsigned long long) * nseg);
+    l.chunk_groups = l.ticket + align_up(sizeof(uint32_t) * kTicketStride);
     l.n_words = l.chunk_groups + align_up(sizeof(int64_t) * nchunk);
     l.total = l.n_words + align_up(sizeof(int64_t));
     return l;
@@ -565,8 +672,8 @@ extern "C" int csbfs_wah_encode(const uint64_t *bits, const uint64_t *mask, int6
                                 void *workspace, size_t ws_bytes, void *stream) {
     if (nbits < 0 || !out || !n_words || !workspace || (nbits > 0 && !bits))
         return fail(CSBFS_EINVAL, "csbfs_wah_encode: null pointer or negative size");
-    if (nbits >= ((int64_t)1 << 37))
-        return fail(CSBFS_EINVAL, "csbfs_wah_encode: nbits too large");
+    if (nbits / kGroupBits > (int64_t)kLbField)
+        return fail(CSBFS_EINVAL, "csbfs_wah_encode: nbits above 63 * (2^29 - 1)");
     if (cap_words < wah_cap(nbits))
         return fail(CSBFS_ENOSPACE, "csbfs_wah_encode: output capacity below floor(nbits/63)+1");
     const WsLayout l = ws_layout(nbits);
@@ -581,13 +688,16 @@ extern "C" int csbfs_wah_encode(const uint64_t *bits, const uint64_t *mask, int6
     b.words_per_piece = (nbits + 63) / 64;
     b.cap = cap_words;
     b.P = 1;
-    b.seg_count = (int32_t *)(ws + l.seg_count);
-    b.seg_first = (int32_t *)(ws + l.seg_first);
+    b.look = (unsigned long long *)(ws + l.look);
+    b.ticket = (uint32_t *)(ws + l.ticket);
     b.nseg = enc_segments(nbits);
     if (nbits == 0) {
         CSBFS_HIP(hipMemsetAsync(n_words, 0, sizeof(int64_t), as_stream(stream)));
         return CSBFS_OK;
     }
+    // the look-back words and tickets start at zero (the caller's workspace
+    // may hold anything)
+    CSBFS_HIP(hipMemsetAsync(ws + l.look, 0, l.chunk_groups - l.look, as_stream(stream)));
     return launch_wah_encode(b, as_stream(stream));
 }
 
