@@ -523,6 +523,7 @@ struct UpdateArgs {
     unsigned long long *part;        // [gridDim][2]: per-workgroup sums
     uint32_t *ticket;                // workgroups done; 0 between levels
     DirArgs dir;
+    unsigned long long *host;        // pinned [2]: the same two sums, for the host
 };
 
 constexpr int kUpdWords = 16;     // bitmap words per wavefront step of the update
@@ -630,6 +631,8 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
         }
         a.total[0] = nf;
         a.total[1] = mf;
+        a.host[0] = nf;
+        a.host[1] = mf;
         choose_direction(a.dir, nf, mf);
         *a.ticket = 0;
     }
@@ -651,12 +654,16 @@ struct SeedArgs {
     int64_t n;
     int64_t words;
     int64_t view_words;
+    uint32_t *zero;      // the search's counters, flags and tickets
+    int64_t zero_words;
 };
 
 __global__ void seed_fill_kernel(SeedArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t top = a.n > a.view_words ? a.n : a.view_words;
+    int64_t top = a.n > a.view_words ? a.n : a.view_words;
+    top = top > a.zero_words ? top : a.zero_words;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < top; k += stride) {
+        if (k < a.zero_words) a.zero[k] = 0;
         if (k < a.n) {
             a.level[k] = -1;
             a.parent[k] = -1;
@@ -729,6 +736,7 @@ struct csbfs_engine {
     LevelCounters lc{};
     int32_t *status = nullptr;
     unsigned long long *host_ctl = nullptr;  // pinned [2][2]: frontier counts, double-buffered
+    unsigned long long *host_ctl_dev = nullptr;  // its device address
     hipEvent_t count_ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> events;
     int32_t last_levels = 0;
@@ -816,16 +824,16 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     e->enc_ticket = reinterpret_cast<uint32_t *>(e->look + e->S * e->nseg);
     ALLOC(e->chunk_groups, sizeof(int64_t) * e->S * e->nchunk);
     ALLOC(e->queue, sizeof(BigItem) * e->queue_cap);
-    ALLOC(e->ctrs, sizeof(uint32_t) * P);
     ALLOC(e->qoff, sizeof(int64_t) * (P + 1));
-    ALLOC(e->status, sizeof(int32_t));
     ALLOC(e->live, sizeof(uint64_t) * words);
     ALLOC(e->upd_part, sizeof(unsigned long long) * 2 * kUpdMaxBlocks);
-    ALLOC(e->upd_ticket, sizeof(uint32_t));
     ALLOC(e->dstate, sizeof(DirState));
+    // everything a search starts from zero, in one block the seed clears:
+    // per-level counters, then the status flag, queue counts and update ticket
     const int64_t slots = (int64_t)max_levels + 1;
     const size_t cnt_bytes = sizeof(unsigned long long) * slots * (2 + P + 1 + 1 + e->S + P) +
-                             sizeof(int64_t) * slots * e->S + sizeof(int32_t) * slots;
+                             sizeof(int64_t) * slots * e->S + sizeof(int32_t) * slots +
+                             sizeof(int32_t) * (2 + P);
     ALLOC(e->counters_mem, cnt_bytes);
 #undef ALLOC
     e->counters_bytes = cnt_bytes;
@@ -849,6 +857,9 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     c += slots * P;
     e->lc.words = (int64_t *)c;
     e->lc.dir = (int32_t *)(e->lc.words + slots * e->S);
+    e->status = e->lc.dir + slots;
+    e->ctrs = reinterpret_cast<uint32_t *>(e->status + 1);
+    e->upd_ticket = e->ctrs + P;
     hipError_t herr = hipMemcpy(e->qoff, qoff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice);
     if (herr != hipSuccess) {
         engine_release(e);
@@ -866,6 +877,11 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
         e->host_ctl = nullptr;
         engine_release(e);
         return hip_fail(herr, "hipHostMalloc", __FILE__, __LINE__);
+    }
+    herr = hipHostGetDevicePointer((void **)&e->host_ctl_dev, e->host_ctl, 0);
+    if (herr != hipSuccess) {
+        engine_release(e);
+        return hip_fail(herr, "hipHostGetDevicePointer", __FILE__, __LINE__);
     }
     for (auto &ev : e->count_ev) {
         herr = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -947,11 +963,8 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     const int32_t dir0 = dense ? kDirDense : bu_only ? kDirBU : kDirTD;
 
     // a0: seed
-    CSBFS_HIP(hipMemsetAsync(e->counters_mem, 0, e->counters_bytes, st));
-    CSBFS_HIP(hipMemsetAsync(e->status, 0, sizeof(int32_t), st));
-    CSBFS_HIP(hipMemsetAsync(e->ctrs, 0, sizeof(uint32_t) * P, st));
-    CSBFS_HIP(hipMemsetAsync(e->upd_ticket, 0, sizeof(uint32_t), st));
-    SeedArgs sa{level, parent, e->pi, e->seen, e->view, n, words, view_words};
+    SeedArgs sa{level, parent, e->pi, e->seen, e->view, n, words, view_words,
+                (uint32_t *)e->counters_mem, (int64_t)(e->counters_bytes / sizeof(uint32_t))};
     const int64_t fill_items = n > view_words ? n : view_words;
     hipLaunchKernelGGL(seed_fill_kernel, dim3(grid_for(fill_items, 256, 8192)), dim3(256), 0, st, sa);
     CSBFS_HIP(hipGetLastError());
@@ -1087,14 +1100,13 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         // adjacency entries; then (last workgroup) the direction of level j + 1
         da.rec = e->lc.dir + sn;
         UpdateArgs ua{e->seen, e->pi, e->f, e->view, level, (int32_t)(j + 1), words, W, (int32_t)P,
-                      e->lc.ctl + 2 * sn, e->ctrs, g->deg, e->upd_part, e->upd_ticket, da};
+                      e->lc.ctl + 2 * sn, e->ctrs, g->deg, e->upd_part, e->upd_ticket, da,
+                      e->host_ctl_dev + 2 * ((j + 1) & 1)};
         hipLaunchKernelGGL(update_kernel, dim3(upd_grid), dim3(kUpdThreads), 0, st, ua);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
-        const int hs = (int)((j + 1) & 1);
-        CSBFS_HIP(hipMemcpyAsync(e->host_ctl + 2 * hs, e->lc.ctl + 2 * sn, 2 * sizeof(unsigned long long),
-                                 hipMemcpyDeviceToHost, st));
-        CSBFS_HIP(hipEventRecord(e->count_ev[hs], st));
+        // the update's last workgroup wrote |f^{j+1}| to host slot (j + 1) & 1
+        CSBFS_HIP(hipEventRecord(e->count_ev[(j + 1) & 1], st));
         return CSBFS_OK;
     };
 
@@ -1114,6 +1126,10 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         const unsigned long long cnt = e->host_ctl[2 * hs];
         if (cnt == 0) break;
         known = cnt;
+        if (k >= n) {  // every level visits a vertex: more than n levels is a broken count
+            CSBFS_HIP(hipStreamSynchronize(st));
+            return fail(CSBFS_ECORRUPT, "csbfs_bfs: frontier counts did not reach zero");
+        }
     }
     const int64_t nl = k + 1;  // levels 0..k
     *n_levels = (int32_t)(nl < INT32_MAX ? nl : INT32_MAX);
