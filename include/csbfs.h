@@ -411,7 +411,10 @@ size_t csbfs_wah_workspace_bytes(int64_t nbits);
  *   bits, mask  device uint64[ceil(nbits/64)]; bits at or past nbits are ignored.
  *   out         device uint64[cap_words], cap_words >= csbfs_wah_capacity(nbits).
  *   n_words     device int64[1]: receives the stream length in words.
- *   workspace   device scratch of ws_bytes >= csbfs_wah_workspace_bytes(nbits).
+ *   workspace   device scratch of ws_bytes >= csbfs_wah_workspace_bytes(nbits);
+ *               any contents (the call clears what it needs); one call at a
+ *               time per workspace.
+ * nbits is at most 63 * (2^29 - 1) (EINVAL above).
  * Asynchronous. Errors: EINVAL, ENOSPACE, EHIP.
  */
 int csbfs_wah_encode(const uint64_t *bits, const uint64_t *mask, int64_t nbits, uint64_t *out,

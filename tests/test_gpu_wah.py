@@ -31,6 +31,8 @@ def _patterns(nbits, rng):
     if nbits > 200000:
         b[70000:140000] = 1    # a 1-run across encoder segments
         b[150001] = 1
+    if nbits > 4000000:
+        b[300000:3000000] = 1  # a 1-run over about 20 segments
     b[-1] = 1
     yield "runs", b
     b = (rng.random(nbits) < 0.5).astype(np.uint8)
@@ -38,7 +40,9 @@ def _patterns(nbits, rng):
     yield "hole", b
 
 
-SIZES = [1, 10, 62, 63, 64, 126, 127, 1000, 4096, 64512, 64513, 129087, 1 << 18, (1 << 20) + 37]
+# up to 66 encoder segments of 2048 groups: the last ones look back past 64
+SIZES = [1, 10, 62, 63, 64, 126, 127, 1000, 4096, 64512, 64513, 129087, 1 << 18, (1 << 20) + 37,
+         (1 << 23) + 12345]
 
 
 @pytest.mark.parametrize("nbits", SIZES)
