@@ -176,12 +176,16 @@ typedef struct csbfs_engine csbfs_engine;
 #define CSBFS_DIR_DENSE 2
 
 /*
- * Allocate the workspace of Algorithm 3 for graph g: visited vector pi,
- * frontier pieces f_i, the temporary t_i, the p frontier views (p * n bits),
+ * Allocate the workspace of Algorithm 3 for graph g: visited vector pi (two
+ * copies, one per level parity; f_i and t_i are formed inside the encoder
+ * and never stored), the p frontier views (p * n bits),
  * the WAH stream arena (p * p streams of floor((n/p)/63) + 1 words, times
  * max_levels with CSBFS_FLAG_KEEP_STREAMS), the expansion work queue and the
  * per-level counters for up to max_levels levels (1 <= max_levels <= 65536).
- * The graph must outlive the engine. Blocking. Errors: EINVAL, EHIP.
+ * The graph must outlive the engine. The encoder's segment size (1024 or
+ * 2048 groups of 63 bits) is chosen from n/p and p; the environment variable
+ * CSBFS_ENC_GPT=2 or 4 fixes it to 1024 or 2048 (same results, other speed).
+ * Blocking. Errors: EINVAL, EHIP.
  */
 int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags,
                         csbfs_engine **out);
@@ -219,8 +223,10 @@ typedef struct csbfs_level_stats {
     int64_t max_rank_bytes;     /* max over i of Alg. 3 bytes sent plus received by P_i */
     int64_t pulled;             /* bottom-up: unvisited vertices that scanned their rows */
     float ms_expand;            /* expansion of f^k (every expansion kernel) (TIMING) */
-    float ms_update;            /* mask, visit update and reduction that follow it (TIMING) */
-    float ms_compress;          /* sieve + WAH encode of the f^k messages (TIMING) */
+    float ms_update;            /* batched: mask, visit update and reduction; csbfs_bfs: 0,
+                                   its update runs inside the encode (TIMING) */
+    float ms_compress;          /* sieve + WAH encode of the f^k messages; csbfs_bfs: with
+                                   the update that forms f^k (TIMING) */
     float ms_decode;            /* decode/merge of the f^k messages (TIMING) */
     int32_t direction;          /* CSBFS_DIR_* used to expand f^k */
     int32_t reserved;

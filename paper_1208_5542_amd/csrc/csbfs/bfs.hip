@@ -33,19 +33,19 @@
 // Processor i's pull reads the column of v in its block-row A_{i,*}; by the
 // symmetry of A that is the row of v in blocks (j, i), which the graph keeps
 // merged per vertex (the pull layout) next to the blocks.
+#include <cstdlib>
 #include <vector>
 
-#include "device.hpp"
+#include "wah_device.hpp"
 #include "graph.hpp"
 
 namespace csbfs {
 namespace {
 
 constexpr int kExpThreads = 256;
-constexpr int kUpdThreads = 1024;
 constexpr int kPullThreads = 256;
 constexpr int kPullRounds = 16;  // per-lane steps (kUnroll entries each) before the wave helps
-constexpr int kEvPerLevel = 5;
+constexpr int kEvPerLevel = 4;  // before/after the update + encode, after the decode, after the expansion
 constexpr int kPullTileDense = 64;  // bitmap words per wave tile of the dense pull
 constexpr int kPullTileBU = 4;      // ... and of the bottom-up pull (many more candidates)
 constexpr int32_t kDirTD = CSBFS_DIR_TOP_DOWN, kDirBU = CSBFS_DIR_BOTTOM_UP, kDirDense = CSBFS_DIR_DENSE;
@@ -507,135 +507,145 @@ __device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsign
     *a.rec = next;
 }
 
-struct UpdateArgs {
+constexpr int kUpdWords = 16;  // bitmap words per wavefront step of the update
+// Groups per encoder thread of a search: 2 (segments of 1024 groups) when
+// segments of 2048 would leave fewer than two workgroups per CU, else 4.
+int search_enc_gpt(int64_t R, int64_t streams) {
+    return streams * enc_segments(R, 4) < 2 * 256 ? 2 : 4;
+}
+static_assert((kEncThreads * 2 * kGroupBits) % 64 == 0, "encoder segments end on word boundaries");
+
+// Per-workgroup sums of the update: new vertices, their adjacency entries.
+__device__ __forceinline__ unsigned long long *update_sums() {
+    __shared__ unsigned long long sums[2];
+    return sums;
+}
+
+// The update of Alg. 3 (t = S and not pi, pi = pi or t, f = t, levels of
+// the new vertices) done inside the encoder of f. The words the encoder
+// stages are S & ~pi_old, so f is never stored. Beside the look-back, the
+// workgroup of stream i -> j clears view (j, i) at the segment's words (the
+// view that stream decodes into) and, with the other p - 1 workgroups of
+// sender i's segment, takes the segment's 16-word steps round-robin: pi for
+// the next level (pi_new = S), then level and adjacency-entry count of every
+// new vertex (lane = vertex; all masked loads of a step in flight before
+// any is summed). pi is double-buffered because every receiver's workgroup
+// reads pi_old while the words are being written.
+struct FrontierHook {
     const uint64_t *S;
-    uint64_t *pi;
-    uint64_t *f;
+    const uint64_t *pi_old;  // visited before level k
+    uint64_t *pi_new;        // visited through level k
     uint64_t *view;
     int32_t *level;
-    int32_t next_level;
-    int64_t words;  // n / 64
-    int64_t W;      // words per processor
+    const int32_t *deg;
+    unsigned long long *part;  // [streams * nseg][2] per-workgroup sums
+    int64_t W;
+    int64_t seg_words;  // bitmap words per encoder segment
     int32_t P;
-    unsigned long long *total;       // [2]: frontier size, its adjacency entries
-    uint32_t *ctrs;                  // [P]: chunk-queue counts, reset for the next level
-    const int32_t *deg;              // [n]: adjacency entries per vertex
-    unsigned long long *part;        // [gridDim][2]: per-workgroup sums
-    uint32_t *ticket;                // workgroups done; 0 between levels
-    DirArgs dir;
-    unsigned long long *host;        // pinned [2]: the same two sums, for the host
+    int32_t lvl;  // k
+
+    __device__ __forceinline__ uint64_t load(const WahBatch &, int64_t, int64_t i, int64_t w) const {
+        const int64_t q = i * W + w;
+        return S[q] & ~pi_old[q];
+    }
+    __device__ __forceinline__ void init() {
+        if (threadIdx.x < 2) update_sums()[threadIdx.x] = 0;
+    }
+    // waves 1.. of the workgroup
+    __device__ void side(const WahBatch &b, int64_t s, int64_t seg, const StreamIdx &x) {
+        const int t = (int)threadIdx.x - 64, nt = (int)blockDim.x - 64;
+        const int lane = threadIdx.x & 63;
+        const int64_t q0 = seg * seg_words;
+        const int64_t q1 = seg == b.nseg - 1 ? W : (q0 + seg_words < W ? q0 + seg_words : W);
+        uint64_t *vw = view + (x.j * P + x.i) * W;
+        for (int64_t q = q0 + t; q < q1; q += nt) vw[q] = 0;
+        const int64_t base = x.i * W;
+        const int64_t nsteps = (q1 - q0 + kUpdWords - 1) / kUpdWords;
+        unsigned long long cnt = 0, dsum = 0;
+        for (int64_t c = x.j + (int64_t)P * (t >> 6); c < nsteps; c += (int64_t)P * (nt >> 6)) {
+            const int64_t qa = q0 + c * kUpdWords;
+            const int64_t qk = qa + lane;
+            uint64_t tk = 0;
+            if (lane < kUpdWords && qk < q1) {
+                const uint64_t sq = S[base + qk];
+                tk = sq & ~pi_old[base + qk];
+                pi_new[base + qk] = sq;
+                cnt += (unsigned long long)__popcll(tk);
+            }
+            int32_t d[kUpdWords];
+#pragma unroll
+            for (int k = 0; k < kUpdWords; ++k) {
+                d[k] = 0;
+                const uint64_t tw = readlane64(tk, k);
+                if ((tw >> lane) & 1) {
+                    const int64_t v = ((base + qa + k) << 6) + lane;
+                    d[k] = deg[v];
+                    level[v] = lvl;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kUpdWords; ++k) dsum += (unsigned long long)d[k];
+        }
+        for (int dd = 32; dd > 0; dd >>= 1) {
+            cnt += (unsigned long long)shfl64((int64_t)cnt, lane ^ dd);
+            dsum += (unsigned long long)shfl64((int64_t)dsum, lane ^ dd);
+        }
+        if (lane == 0 && (cnt | dsum)) {
+            atomicAdd(&update_sums()[0], cnt);
+            atomicAdd(&update_sums()[1], dsum);
+        }
+    }
+    // thread 0, after the workgroup's last barrier
+    __device__ __forceinline__ void finish(const WahBatch &b, int64_t s, int64_t seg) {
+        part[2 * (s * b.nseg + seg)] = update_sums()[0];
+        part[2 * (s * b.nseg + seg) + 1] = update_sums()[1];
+    }
 };
 
-constexpr int kUpdWords = 16;     // bitmap words per wavefront step of the update
-// Workgroups of the update (their sums meet in one): one per CU. Each
-// workgroup's release of its sums writes back its XCD's L2, so the update
-// uses few large workgroups rather than many small ones.
-constexpr int kUpdMaxBlocks = 256;
+// Update + sieve + compress of level k (k >= 1): one workgroup per (stream,
+// segment). Returns at once once the search has ended.
+template <int kGpt>
+__global__ __launch_bounds__(kEncThreads) void frontier_encode_kernel(WahBatch b, FrontierHook h,
+                                                                      const DirState *st) {
+    if (st->cur == kDirIdle) return;
+    encode_segment<kGpt>(b, h);
+}
 
-// A wavefront takes kUpdWords consecutive bitmap words at a time: lane k
-// (< kUpdWords) handles word q0 + k (t = S & ~pi, pi = S, f = t); the wave
-// clears the P views at those words, then writes the level of every new
-// vertex word by word (lane = vertex) and reads its adjacency-entry count.
-// Branches on a word's t are uniform over the wave. Each workgroup stores
-// its sums; the last one to finish adds them up, stores the level's
-// counters and chooses the next level's direction.
-__global__ __launch_bounds__(kUpdThreads) void update_kernel(UpdateArgs a) {
-    // An empty frontier visits nothing. No workgroup reads the state after
-    // the last one rewrites it: that one runs after every ticket is taken.
-    if (a.dir.st->cur == kDirIdle) return;
-    const int lane = threadIdx.x & 63;
-    if (blockIdx.x == 0 && threadIdx.x < a.P) a.ctrs[threadIdx.x] = 0;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    unsigned long long cnt = 0, dsum = 0;
-    for (int64_t q0 = wave * kUpdWords; q0 < a.words; q0 += nwaves * kUpdWords) {
-        const int64_t qk = q0 + lane;
-        uint64_t tk = 0;
-        if (lane < kUpdWords && qk < a.words) {
-            const uint64_t p = a.pi[qk], sq = a.S[qk];
-            tk = sq & ~p;
-            if (tk) a.pi[qk] = sq;
-            a.f[qk] = tk;
-            cnt += (unsigned long long)__popcll(tk);
-        }
-        // processor i's views (i, j) at these words, kUpdWords consecutive per j
-        for (int idx = lane; idx < kUpdWords * a.P; idx += 64) {
-            const int64_t q = q0 + (idx % kUpdWords);
-            const int32_t j = idx / kUpdWords;
-            if (q < a.words) {
-                const int64_t i = q / a.W, ql = q - i * a.W;
-                a.view[(i * a.P + j) * a.W + ql] = 0;
-            }
-        }
-        // all the masked loads of the step are in flight before any is summed
-        int32_t d[kUpdWords];
-#pragma unroll
-        for (int k = 0; k < kUpdWords; ++k) {
-            d[k] = 0;
-            const uint64_t t = readlane64(tk, k);
-            if ((t >> lane) & 1) {
-                const int64_t v = ((q0 + k) << 6) + lane;
-                d[k] = a.deg[v];
-                a.level[v] = a.next_level;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kUpdWords; ++k) dsum += (unsigned long long)d[k];
-    }
-    for (int dd = 32; dd > 0; dd >>= 1) {
-        cnt += (unsigned long long)shfl64((int64_t)cnt, lane ^ dd);
-        dsum += (unsigned long long)shfl64((int64_t)dsum, lane ^ dd);
-    }
-    __shared__ unsigned long long red[2][kUpdThreads / 64];
-    __shared__ bool last;
-    const int w = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][w] = cnt;
-        red[1][w] = dsum;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long s0 = 0, s1 = 0;
-        for (int k = 0; k < kUpdThreads / 64; ++k) {
-            s0 += red[0][k];
-            s1 += red[1][k];
-        }
-        __hip_atomic_store(&a.part[2 * blockIdx.x], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.part[2 * blockIdx.x + 1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    unsigned long long s0 = 0, s1 = 0;
-    for (int64_t b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
-        s0 += __hip_atomic_load(&a.part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s1 += __hip_atomic_load(&a.part[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    for (int dd = 32; dd > 0; dd >>= 1) {
-        s0 += (unsigned long long)shfl64((int64_t)s0, lane ^ dd);
-        s1 += (unsigned long long)shfl64((int64_t)s1, lane ^ dd);
-    }
-    __syncthreads();
-    if (lane == 0) {
-        red[0][w] = s0;
-        red[1][w] = s1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+struct ReduceArgs {
+    const unsigned long long *part;  // [nparts][2] sums of the update's workgroups
+    int64_t nparts;
+    unsigned long long *total;       // [2]: |f^k| and its adjacency entries (level counters)
+    unsigned long long *host;        // pinned [2]: the same, for the host
+    uint32_t *ctrs;                  // [P]: chunk-queue counts, cleared for the expansion
+    int32_t P;
+    DirArgs dir;
+};
+
+// Decode of level k into the views; workgroup (0, 0) first reduces the
+// update's sums, stores the level's counters, writes |f^k| for the host and
+// chooses the direction of the expansion of f^k. A workgroup that starts
+// after that choice and finds the idle direction has an empty frontier's
+// streams to decode, which set no bit: returning is the same.
+__global__ __launch_bounds__(kDecThreads) void search_decode_kernel(WahBatch b, ReduceArgs r) {
+    if (r.dir.st->cur == kDirIdle) return;
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
         unsigned long long nf = 0, mf = 0;
-        for (int k = 0; k < kUpdThreads / 64; ++k) {
-            nf += red[0][k];
-            mf += red[1][k];
+        for (int64_t k = threadIdx.x; k < r.nparts; k += blockDim.x) {
+            nf += r.part[2 * k];
+            mf += r.part[2 * k + 1];
         }
-        a.total[0] = nf;
-        a.total[1] = mf;
-        a.host[0] = nf;
-        a.host[1] = mf;
-        choose_direction(a.dir, nf, mf);
-        *a.ticket = 0;
+        nf = (unsigned long long)block_reduce((long long)nf, SumI64(), 0LL);
+        mf = (unsigned long long)block_reduce((long long)mf, SumI64(), 0LL);
+        if (threadIdx.x < r.P) r.ctrs[threadIdx.x] = 0;
+        if (threadIdx.x == 0) {
+            r.total[0] = nf;
+            r.total[1] = mf;
+            r.host[0] = nf;
+            r.host[1] = mf;
+            choose_direction(r.dir, nf, mf);
+        }
     }
+    dec_scatter_body(b);
 }
 
 // Vertices with at least one adjacency entry, one bit each.
@@ -722,7 +732,9 @@ struct csbfs_engine {
     int32_t L = 0;
     uint32_t flags = 0;
     int64_t S = 0, cap = 0, nseg = 0, nchunk = 0;
-    uint64_t *pi = nullptr, *f = nullptr, *seen = nullptr, *view = nullptr, *arena = nullptr;
+    int enc_gpt = 4;  // groups per encoder thread (segment size)
+    uint64_t *pi[2] = {nullptr, nullptr};  // visited vertices, by level parity
+    uint64_t *seen = nullptr, *view = nullptr, *arena = nullptr;
     unsigned long long *look = nullptr;  // encoder look-back words [S * nseg]
     uint32_t *enc_ticket = nullptr;      // [kTicketStride * S], after look
     size_t look_bytes = 0;
@@ -741,8 +753,7 @@ struct csbfs_engine {
     std::vector<hipEvent_t> events;
     int32_t last_levels = 0;
     uint64_t *live = nullptr;    // [n / 64]: vertices with adjacency entries
-    unsigned long long *upd_part = nullptr;  // [kUpdMaxBlocks][2]
-    uint32_t *upd_ticket = nullptr;
+    unsigned long long *part = nullptr;  // [S * nseg][2]: sums of the update's workgroups
     DirState *dstate = nullptr;
     // Beamer's parameters of the per-level direction choice, measured best
     // on R-MAT graphs of scale 22 (4 x 4) and 26 (8 x 8)
@@ -796,7 +807,12 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     const int64_t P = g->P, n = g->n;
     e->S = P * P;
     e->cap = wah_cap(g->R);
-    e->nseg = enc_segments(g->R);
+    e->enc_gpt = search_enc_gpt(g->R, e->S);
+    if (const char *ev = std::getenv("CSBFS_ENC_GPT")) {  // fixed segment size (tests, tuning)
+        if (ev[0] == '2' && ev[1] == 0) e->enc_gpt = 2;
+        if (ev[0] == '4' && ev[1] == 0) e->enc_gpt = 4;
+    }
+    e->nseg = enc_segments(g->R, e->enc_gpt);
     e->nchunk = dec_chunks(g->R);
     const int64_t words = n / 64;
     const int64_t arena_slots = (flags & CSBFS_FLAG_KEEP_STREAMS) ? (int64_t)max_levels + 1 : 1;
@@ -813,8 +829,8 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
         }                                                                  \
         ptr = reinterpret_cast<decltype(ptr)>(_p);                         \
     } while (0)
-    ALLOC(e->pi, sizeof(uint64_t) * words);
-    ALLOC(e->f, sizeof(uint64_t) * words);
+    ALLOC(e->pi[0], sizeof(uint64_t) * words);
+    ALLOC(e->pi[1], sizeof(uint64_t) * words);
     ALLOC(e->seen, sizeof(uint64_t) * words);
     ALLOC(e->view, sizeof(uint64_t) * P * words);
     ALLOC(e->arena, sizeof(uint64_t) * e->S * e->cap * arena_slots);
@@ -826,7 +842,7 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     ALLOC(e->queue, sizeof(BigItem) * e->queue_cap);
     ALLOC(e->qoff, sizeof(int64_t) * (P + 1));
     ALLOC(e->live, sizeof(uint64_t) * words);
-    ALLOC(e->upd_part, sizeof(unsigned long long) * 2 * kUpdMaxBlocks);
+    ALLOC(e->part, sizeof(unsigned long long) * 2 * e->S * e->nseg);
     ALLOC(e->dstate, sizeof(DirState));
     // everything a search starts from zero, in one block the seed clears:
     // per-level counters, then the status flag, queue counts and update ticket
@@ -859,7 +875,6 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     e->lc.dir = (int32_t *)(e->lc.words + slots * e->S);
     e->status = e->lc.dir + slots;
     e->ctrs = reinterpret_cast<uint32_t *>(e->status + 1);
-    e->upd_ticket = e->ctrs + P;
     hipError_t herr = hipMemcpy(e->qoff, qoff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice);
     if (herr != hipSuccess) {
         engine_release(e);
@@ -963,7 +978,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     const int32_t dir0 = dense ? kDirDense : bu_only ? kDirBU : kDirTD;
 
     // a0: seed
-    SeedArgs sa{level, parent, e->pi, e->seen, e->view, n, words, view_words,
+    SeedArgs sa{level, parent, e->pi[0], e->seen, e->view, n, words, view_words,
                 (uint32_t *)e->counters_mem, (int64_t)(e->counters_bytes / sizeof(uint32_t))};
     const int64_t fill_items = n > view_words ? n : view_words;
     hipLaunchKernelGGL(seed_fill_kernel, dim3(grid_for(fill_items, 256, 8192)), dim3(256), 0, st, sa);
@@ -978,7 +993,6 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     ea.row_ptr = g->row_ptr;
     ea.col_base = g->col_base;
     ea.col = g->col;
-    ea.pi = e->pi;
     ea.S = e->seen;
     ea.parent = parent;
     ea.queue = e->queue;
@@ -991,7 +1005,6 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     ea.dir = &e->dstate->cur;
     PullArgs pa{};
     pa.S = e->seen;
-    pa.pi = e->pi;
     pa.live = e->live;
     pa.view = e->view;
     pa.pull_off = g->pull_off;
@@ -1010,7 +1023,6 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     const unsigned exp_grid = 2048, big_grid = 2048;
     const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
     const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 2048);
-    const unsigned upd_grid = grid_for((words + kUpdWords - 1) / kUpdWords, kUpdThreads / 64, kUpdMaxBlocks);
     DirArgs da{};
     da.st = e->dstate;
     da.n = n;
@@ -1019,8 +1031,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     da.beta = e->beta;
     da.force = force;
 
-    WahBatch wb{};
-    wb.bits_base = e->f;
+    WahBatch wb{};  // the words come from FrontierHook, not from a bits buffer
     wb.mask_base = (e->flags & CSBFS_FLAG_NO_SIEVE) ? nullptr : g->dir;
     wb.nbits = R;
     wb.words_per_piece = W;
@@ -1034,35 +1045,54 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     wb.chunk_starts = 1;  // the decode reads the chunk starts the encode records
     wb.dst_base = e->view;
     wb.status = e->status;
-    wb.plane_count = &e->dstate->prev;  // |f^j| in iteration j: no message once it is 0
+    const dim3 enc_grid((unsigned)e->nseg, (unsigned)S), dec_grid((unsigned)e->nchunk, (unsigned)S);
 
-    // Iteration j: the messages carrying f^j (j >= 1: sieve + compress, then
-    // decode into the views), the expansion of f^j, the update producing
-    // f^{j+1} and the copy of |f^{j+1}| to host slot (j + 1) & 1.
+    // Iteration j: for j >= 1 the update that forms f^j together with the
+    // sieve and compression of its messages, then their decode into the views
+    // (whose first workgroup reduces |f^j|, writes it to host slot j & 1 and
+    // chooses the direction); then the expansion of f^j. pi[j & 1] holds the
+    // vertices visited through level j.
     auto enqueue_iter = [&](int64_t j, unsigned long long known) -> int {
-        const int64_t sj = slot_of(e, j), sn = slot_of(e, j + 1);
-        if (j + 1 >= e->L) {
+        const int64_t sj = slot_of(e, j);
+        if (j >= e->L) {
             const int r2 = reset_overflow_slot(e, st);
             if (r2) return r2;
         }
-        hipEvent_t *evp = (timing && j >= 1 && j - 1 < e->L) ? &e->events[(size_t)(j - 1) * kEvPerLevel] : nullptr;
         hipEvent_t *ev = (timing && j < e->L) ? &e->events[(size_t)j * kEvPerLevel] : nullptr;
+        uint64_t *pi_j = e->pi[j & 1];
+        if (ev) CSBFS_HIP(hipEventRecord(ev[0], st));
         if (j >= 1) {
-            // a4 + a5: sieve and compress every stream i -> j
+            // a2 + a4 + a5: t = S & ~pi, levels, sieve and compress every stream i -> j
             const int64_t arena_slot = keep ? sj : 0;
             wb.out_base = e->arena + arena_slot * S * e->cap;
             wb.n_words = e->lc.words + sj * S;
             wb.stat_sieved_bits = e->lc.sbits + sj * S;
             wb.stat_unsieved_words = e->lc.uwords + sj * P;
-            int r2 = launch_wah_encode(wb, st);
-            if (r2) return r2;
-            if (evp) CSBFS_HIP(hipEventRecord(evp[3], st));
-            // a6: the stream slots are the receive buffers; a7: decode into the views
-            r2 = launch_wah_decode(wb, st);
-            if (r2) return r2;
-            if (evp) CSBFS_HIP(hipEventRecord(evp[4], st));
+            FrontierHook fh{e->seen, e->pi[(j + 1) & 1], pi_j, e->view, level, g->deg, e->part, W,
+                            (int64_t)kEncThreads * e->enc_gpt * kGroupBits / 64, (int32_t)P, (int32_t)j};
+            if (e->enc_gpt == 2)
+                hipLaunchKernelGGL(frontier_encode_kernel<2>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
+                                   (const DirState *)e->dstate);
+            else
+                hipLaunchKernelGGL(frontier_encode_kernel<4>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
+                                   (const DirState *)e->dstate);
+            CSBFS_HIP(hipGetLastError());
+            if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
+            // a6: the stream slots are the receive buffers; a7: decode into the
+            // views; a3: reduction of |f^j|, direction of its expansion
+            da.rec = e->lc.dir + sj;
+            ReduceArgs ra{e->part, S * e->nseg, e->lc.ctl + 2 * sj, e->host_ctl_dev + 2 * (j & 1), e->ctrs,
+                          (int32_t)P, da};
+            hipLaunchKernelGGL(search_decode_kernel, dec_grid, dim3(kDecThreads), 0, st, wb, ra);
+            CSBFS_HIP(hipGetLastError());
+            CSBFS_HIP(hipEventRecord(e->count_ev[j & 1], st));
+        } else if (ev) {
+            CSBFS_HIP(hipEventRecord(ev[1], st));
         }
-        if (ev) CSBFS_HIP(hipEventRecord(ev[0], st));
+        if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
+        ea.pi = pi_j;
+        pa.pi = pi_j;
+        pb.pi = pi_j;
         // a1: expand f^j; small tiles when the last known frontier is large,
         // so that every wave gets work, large ones when it is small
         const bool wide = (double)known * 64.0 >= (double)n;
@@ -1095,43 +1125,34 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
                 CSBFS_HIP(hipGetLastError());
             }
         }
-        if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
-        // a2: mask, visit, f^{j+1}; a3: reduction of |f^{j+1}| and of its
-        // adjacency entries; then (last workgroup) the direction of level j + 1
-        da.rec = e->lc.dir + sn;
-        UpdateArgs ua{e->seen, e->pi, e->f, e->view, level, (int32_t)(j + 1), words, W, (int32_t)P,
-                      e->lc.ctl + 2 * sn, e->ctrs, g->deg, e->upd_part, e->upd_ticket, da,
-                      e->host_ctl_dev + 2 * ((j + 1) & 1)};
-        hipLaunchKernelGGL(update_kernel, dim3(upd_grid), dim3(kUpdThreads), 0, st, ua);
-        CSBFS_HIP(hipGetLastError());
-        if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
-        // the update's last workgroup wrote |f^{j+1}| to host slot (j + 1) & 1
-        CSBFS_HIP(hipEventRecord(e->count_ev[(j + 1) & 1], st));
+        if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
         return CSBFS_OK;
     };
 
-    // The host reads |f^{k+1}| while iteration k + 1 already runs on the GPU
-    // (one level of look-ahead). When f^{k+1} turns out empty, the update
-    // that found it chose the idle direction: every kernel of that iteration
-    // returned at once, and its counters lie past the last reported level.
+    // The host reads |f^k| (written by the decode of level k) while the
+    // expansion of level k and iteration k + 1 are already queued. When f^k
+    // is empty the decode chose the idle direction: the expansion of level k
+    // and every kernel of iteration k + 1 return at once, and their counters
+    // lie past the last reported level.
     unsigned long long known = 1;  // |f^0|
     rc = enqueue_iter(0, known);
     if (rc) return rc;
-    int64_t k = 0;
-    for (;; ++k) {
+    rc = enqueue_iter(1, known);
+    if (rc) return rc;
+    int64_t k = 1;
+    for (;;) {
         rc = enqueue_iter(k + 1, known);
         if (rc) return rc;
-        const int hs = (int)((k + 1) & 1);
-        CSBFS_HIP(hipEventSynchronize(e->count_ev[hs]));
-        const unsigned long long cnt = e->host_ctl[2 * hs];
+        CSBFS_HIP(hipEventSynchronize(e->count_ev[k & 1]));
+        const unsigned long long cnt = e->host_ctl[2 * (k & 1)];
         if (cnt == 0) break;
         known = cnt;
-        if (k >= n) {  // every level visits a vertex: more than n levels is a broken count
+        if (++k > n) {  // every level visits a vertex: more than n levels is a broken count
             CSBFS_HIP(hipStreamSynchronize(st));
             return fail(CSBFS_ECORRUPT, "csbfs_bfs: frontier counts did not reach zero");
         }
     }
-    const int64_t nl = k + 1;  // levels 0..k
+    const int64_t nl = k;  // levels 0..k-1
     *n_levels = (int32_t)(nl < INT32_MAX ? nl : INT32_MAX);
     e->last_levels = *n_levels;
 
@@ -1212,22 +1233,18 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         }
     }
     if (timing) {
-        for (int64_t lv = 0; lv < nl && lv < e->L; ++lv) {
+        // the update of f^k runs inside its encoder: ms_update stays 0 and
+        // ms_compress holds update + sieve + compress of level k
+        for (int64_t lv = 0; lv < want; ++lv) {
             hipEvent_t *ev = &e->events[(size_t)lv * kEvPerLevel];
-            float a = 0, b = 0;
-            CSBFS_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
-            CSBFS_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
-            if (lv < want) {
-                stats[lv].ms_expand = a;
-                stats[lv].ms_update = b;
-            }
-            if (lv + 1 < nl && lv + 1 < want) {
-                float c = 0, d = 0;
-                CSBFS_HIP(hipEventElapsedTime(&c, ev[2], ev[3]));
-                CSBFS_HIP(hipEventElapsedTime(&d, ev[3], ev[4]));
-                stats[lv + 1].ms_compress = c;
-                stats[lv + 1].ms_decode = d;
-            }
+            float c = 0, d = 0, x = 0;
+            CSBFS_HIP(hipEventElapsedTime(&c, ev[0], ev[1]));
+            CSBFS_HIP(hipEventElapsedTime(&d, ev[1], ev[2]));
+            CSBFS_HIP(hipEventElapsedTime(&x, ev[2], ev[3]));
+            stats[lv].ms_compress = c;
+            stats[lv].ms_decode = d;
+            stats[lv].ms_expand = x;
+            stats[lv].ms_update = 0.f;
         }
     }
     return CSBFS_OK;

@@ -49,9 +49,12 @@ constexpr int kDecWpt = 4;
 constexpr int kDecChunk = kDecThreads * kDecWpt;
 
 inline int64_t wah_cap(int64_t nbits) { return nbits / kGroupBits + 1; }
-inline int64_t enc_segments(int64_t nbits) {
+// Segments of an encoder with gpt groups per thread (kEncGpt by default;
+// searches on small pieces take 2 to get more workgroups).
+inline int64_t enc_segments(int64_t nbits, int gpt = kEncGpt) {
     int64_t G = nbits / kGroupBits;
-    return G == 0 ? 1 : (G + kEncSeg - 1) / kEncSeg;
+    const int64_t seg = (int64_t)kEncThreads * gpt;
+    return G == 0 ? 1 : (G + seg - 1) / seg;
 }
 inline int64_t dec_chunks(int64_t nbits) { return (wah_cap(nbits) + kDecChunk - 1) / kDecChunk; }
 

@@ -115,6 +115,24 @@ def test_search_matches_oracle(scale, p, nroots, mode):
         _check_search(eng, g, n, p, src, dst, int(root), adj, V)
 
 
+@pytest.mark.parametrize("gpt", ["2", "4"])
+def test_encoder_segment_sizes(gpt, monkeypatch):
+    """Both segment sizes of the search's encoder (1024 and 2048 groups), on
+    pieces of several segments: R-MAT scale 20 on a 4 x 4 grid (2^18 bits per
+    piece), streams byte-identical to the oracle's Algorithm 3."""
+    from paper_1208_5542_amd import csbfs
+    monkeypatch.setenv("CSBFS_ENC_GPT", gpt)
+    scale, p = 20, 4
+    n, src, dst = _graph(scale)
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    eng = csbfs.Engine(g, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS)
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst).reshape(-1)
+    for root in inputs.pick_roots(n, src, dst, 2, inputs.graph_seed(scale) + 2):
+        log(f"search scale={scale} p={p} segment groups={512 * int(gpt)} root={int(root)}")
+        _check_search(eng, g, n, p, src, dst, int(root), adj, V)
+
+
 def test_sparse_graph_many_levels():
     """A long path plus random chords: many levels, tiny frontiers."""
     from paper_1208_5542_amd import csbfs
