@@ -377,7 +377,8 @@ def main():
     inv_ratio, nlev = 0.0, 0
     exp_bytes, exp_ms, exp_launches = 0, 0.0, 0
     dir_count = {"top_down": 0, "bottom_up": 0}
-    cat_ms = {"expand": 0.0, "update": 0.0, "compress": 0.0, "decode": 0.0}
+    # the search forms f^k inside the encoder of its messages: one category
+    cat_ms = {"expand": 0.0, "update_compress": 0.0, "decode": 0.0}
     R = n // p
     for _, nl, stats, _m in per_root:
         for k, s in enumerate(stats):
@@ -400,8 +401,7 @@ def main():
             exp_ms += s["ms_expand"]
             exp_launches += 1
             cat_ms["expand"] += s["ms_expand"]
-            cat_ms["update"] += s["ms_update"]
-            cat_ms["compress"] += s["ms_compress"]
+            cat_ms["update_compress"] += s["ms_update"] + s["ms_compress"]
             cat_ms["decode"] += s["ms_decode"]
     if p > 1:
         ratio = tot["raw_bytes"] / max(tot["wah_sieved_bytes"], 1)
