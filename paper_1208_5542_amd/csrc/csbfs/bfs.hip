@@ -72,7 +72,8 @@ struct ExpandArgs {
     BigItem *queue;
     const int64_t *qoff;       // [P + 1]: processor r's chunk queue is queue[qoff[r], qoff[r+1])
     uint32_t *queue_count;     // [P] items pushed
-    int32_t tile_words;        // view words per tile (<= 64)
+    int32_t tile_words;        // view words per tile (<= 64), read from *tile at kernel entry
+    const int32_t *tile;       // device: tile width chosen with the level's direction
     int64_t R;
     int64_t W;
     int32_t P;
@@ -239,6 +240,7 @@ template <bool kDense>
 __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
     const int32_t d = *a.dir;
     if (d == kDirBU || d == kDirIdle) return;
+    a.tile_words = *a.tile;
     expand_body<kDense>(a);
 }
 
@@ -459,16 +461,19 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
 static_assert(kExpThreads == kPullThreads, "one block size for both directions");
 __global__ __launch_bounds__(kExpThreads) void level_kernel(ExpandArgs ea, PullArgs pa) {
     const int32_t d = *ea.dir;
-    if (d == kDirBU)
+    if (d == kDirBU) {
         pull_body<true>(pa);
-    else if (d != kDirIdle)
+    } else if (d != kDirIdle) {
+        ea.tile_words = *ea.tile;
         expand_body<false>(ea);
+    }
 }
 
 // Direction state carried from level to level on the device.
 struct DirState {
     int32_t cur;              // direction of the level expanded next
-    int32_t pad;
+    int32_t tile;             // view words per top-down tile of that level: 64, or
+                              // 16 when the frontier holds n/64 vertices or more
     unsigned long long vdeg;  // adjacency entries of the visited vertices
     unsigned long long prev;  // size of the newest frontier (compared with the next one)
 };
@@ -503,6 +508,7 @@ __device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsign
     }
     s.prev = nf;
     s.cur = next;
+    s.tile = (double)nf * 64.0 >= (double)a.n ? 16 : 64;
     *a.st = s;
     *a.rec = next;
 }
@@ -693,7 +699,7 @@ __global__ void seed_root_kernel(SeedArgs a, int64_t root, int64_t R, int64_t W,
     const int64_t own = root / R, rl = root - own * R;
     DirState s;
     s.cur = dir0;
-    s.pad = 0;
+    s.tile = 64;
     s.vdeg = (unsigned long long)deg[root];
     s.prev = 1;
     *ds = s;
@@ -1003,6 +1009,8 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     ea.P = (int32_t)P;
     ea.status = e->status;
     ea.dir = &e->dstate->cur;
+    ea.tile = &e->dstate->tile;
+    ea.tile_words = 64;
     PullArgs pa{};
     pa.S = e->seen;
     pa.live = e->live;
@@ -1052,7 +1060,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     // (whose first workgroup reduces |f^j|, writes it to host slot j & 1 and
     // chooses the direction); then the expansion of f^j. pi[j & 1] holds the
     // vertices visited through level j.
-    auto enqueue_iter = [&](int64_t j, unsigned long long known) -> int {
+    auto enqueue_iter = [&](int64_t j) -> int {
         const int64_t sj = slot_of(e, j);
         if (j >= e->L) {
             const int r2 = reset_overflow_slot(e, st);
@@ -1093,10 +1101,7 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         ea.pi = pi_j;
         pa.pi = pi_j;
         pb.pi = pi_j;
-        // a1: expand f^j; small tiles when the last known frontier is large,
-        // so that every wave gets work, large ones when it is small
-        const bool wide = (double)known * 64.0 >= (double)n;
-        ea.tile_words = wide ? 16 : 64;
+        // a1: expand f^j (tile width and direction chosen on the device)
         ea.edges = e->lc.edges + sj;
         if (dense) {
             hipLaunchKernelGGL(expand_kernel<true>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
@@ -1134,19 +1139,17 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     // is empty the decode chose the idle direction: the expansion of level k
     // and every kernel of iteration k + 1 return at once, and their counters
     // lie past the last reported level.
-    unsigned long long known = 1;  // |f^0|
-    rc = enqueue_iter(0, known);
+    rc = enqueue_iter(0);
     if (rc) return rc;
-    rc = enqueue_iter(1, known);
+    rc = enqueue_iter(1);
     if (rc) return rc;
     int64_t k = 1;
     for (;;) {
-        rc = enqueue_iter(k + 1, known);
+        rc = enqueue_iter(k + 1);
         if (rc) return rc;
         CSBFS_HIP(hipEventSynchronize(e->count_ev[k & 1]));
         const unsigned long long cnt = e->host_ctl[2 * (k & 1)];
         if (cnt == 0) break;
-        known = cnt;
         if (++k > n) {  // every level visits a vertex: more than n levels is a broken count
             CSBFS_HIP(hipStreamSynchronize(st));
             return fail(CSBFS_ECORRUPT, "csbfs_bfs: frontier counts did not reach zero");
