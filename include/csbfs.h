@@ -194,7 +194,8 @@ int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags
  * Parameters of the per-level direction choice (Beamer, Asanovic and
  * Patterson's rule). After the update that produced f^{k+1}, with m_f the
  * adjacency entries of f^{k+1} and m_u those of the still unvisited
- * vertices: a top-down search turns bottom-up when m_f * alpha > m_u; a
+ * vertices: a top-down search turns bottom-up when m_f * alpha > m_u and
+ * the frontier did not shrink; a
  * bottom-up search turns top-down again when |f^{k+1}| * beta < n and the
  * frontier shrank. Level 0 is top-down. alpha <= 0 keeps every level
  * top-down. Defaults: alpha = 8, beta = 24. Takes effect at the next

@@ -3,7 +3,8 @@
 // pi_i and frontier piece f_i (R bits each), the "seen" bits S_i (pi_i plus
 // the vertices discovered during the current level), and its P incoming
 // frontier pieces f_{i,j}, the "views" (bits of R_j as received from P_j).
-// One level k:
+// Level k (launch order: update + sieve + compress, decode + reduction,
+// expansion):
 //
 //   expand   t_i = sum_j A_{i,j} (x) f_{i,j} over the (select, max) semiring
 //            (Sec. III.A: the highest-labelled frontier neighbour wins).
@@ -18,17 +19,18 @@
 //              dense:  a top-down push that only sets S bits (a bitmap small
 //                      enough to stay in L2), then every new v pulls its
 //                      parent as in bottom-up.
-//            By default each level is top-down or bottom-up: after the
-//            update, a one-thread kernel applies Beamer's rule to the new
-//            frontier's size and adjacency entries and stores the direction
-//            of the next level on the device, where every expansion kernel
-//            reads it (the kernels not chosen return at once).
-//   update   t_i = S_i & ~pi_i; pi_i = S_i; f_i = t_i; level[v] = k + 1; the
-//            frontier size is reduced into a counter that the host reads;
-//            the views are cleared for the next level's messages.
-//   sieve + compress   stream i -> j = WAH-64(f_i AND V_{j,i})  (wah.hip)
+//            By default each level is top-down or bottom-up: the
+//            reduction applies Beamer's rule to the frontier's size and
+//            adjacency entries and stores the direction (and the top-down
+//            tile width) on the device, where the expansion reads it.
+//   update   f_i = S_i & ~pi_i, formed while the encoder stages it (never
+//            stored); pi_i = S_i (the other parity's copy); level[v] = k;
+//            the views are cleared for this level's messages.
+//   sieve + compress   stream i -> j = WAH-64(f_i AND V_{j,i})
 //   exchange           stream slot (i, j) is P_j's receive buffer from P_i
-//   decode/merge       view (j, i) |= WAH^-1(stream i -> j)    (wah.hip)
+//   decode/merge       view (j, i) |= WAH^-1(stream i -> j); the decode's
+//                      first workgroup reduces |f| (read by the host) and
+//                      chooses the direction.
 //
 // Processor i's pull reads the column of v in its block-row A_{i,*}; by the
 // symmetry of A that is the row of v in blocks (j, i), which the graph keeps
@@ -502,7 +504,10 @@ __device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsign
     } else if (a.force >= 0) {
         next = a.force;
     } else if (s.cur == kDirTD) {
-        if (a.alpha > 0.f && (double)mf * (double)a.alpha > mu) next = kDirBU;
+        // only while the frontier does not shrink: near the end the unvisited
+        // entries are mostly other components', and m_u alone would pull
+        // (scanning those components' rows) on a frontier of a few vertices
+        if (a.alpha > 0.f && (double)mf * (double)a.alpha > mu && nf >= s.prev) next = kDirBU;
     } else if ((double)nf * (double)a.beta < (double)a.n && nf < s.prev) {
         next = kDirTD;
     }
