@@ -1032,8 +1032,10 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     PullArgs pb = pa;
     pa.tile_words = kPullTileDense;
     pb.tile_words = kPullTileBU;
-    // one resident wave per SIMD slot of every CU, a multiple of the XCD count
-    const unsigned exp_grid = 2048, big_grid = 2048;
+    // grids (multiples of the XCD count) from a sweep at scales 22 and 26:
+    // 1024 expansion workgroups (4 waves each) and 512 for the long rows beat
+    // 512-4096 and 512-2048 (scale 26: 218 -> 237 GTEPS)
+    const unsigned exp_grid = 1024, big_grid = 512;
     const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
     const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 2048);
     DirArgs da{};
