@@ -245,8 +245,8 @@ typedef struct csbfs_level_stats {
  *           k < min(n_levels, stats_cap, max_levels of the engine).
  *   n_levels host: number of levels (max level + 1), whatever stats_cap is.
  *
- * Blocking: the level loop reads the frontier size back after each update
- * (the "reducing" step of Sec. VII.B). Concurrent calls on one engine race;
+ * Blocking: the level loop reads each level's frontier size back (the
+ * "reducing" step of Sec. VII.B), one level behind the GPU. Concurrent calls on one engine race;
  * distinct engines may run concurrently on distinct streams. Errors: EINVAL,
  * ERANGE (root outside [0, n)), ECORRUPT, EHIP.
  */
