@@ -49,7 +49,7 @@ constexpr int kPullThreads = 256;
 constexpr int kPullRounds = 16;  // per-lane steps (kUnroll entries each) before the wave helps
 constexpr int kEvPerLevel = 4;  // before/after the update + encode, after the decode, after the expansion
 constexpr int kPullTileDense = 64;  // bitmap words per wave tile of the dense pull
-constexpr int kPullTileBU = 4;      // ... and of the bottom-up pull (many more candidates)
+constexpr int kPullTileBU = 8;      // ... and of the bottom-up pull (many more candidates; 8 beat 2 and 4)
 constexpr int32_t kDirTD = CSBFS_DIR_TOP_DOWN, kDirBU = CSBFS_DIR_BOTTOM_UP, kDirDense = CSBFS_DIR_DENSE;
 // No frontier left: every kernel of the iteration returns at once (the
 // host learns of it one iteration late, and that iteration costs nothing).
@@ -85,7 +85,7 @@ struct ExpandArgs {
 };
 
 
-constexpr int kUnroll = 4;  // independent edges in flight per lane
+constexpr int kUnroll = 2;  // independent edges in flight per lane (2 beat 4 and 8: scale 26 237 -> 253 GTEPS)
 
 // Relax kUnroll (target v, source u) pairs; every load is issued before any
 // result is used, so their latencies overlap.
