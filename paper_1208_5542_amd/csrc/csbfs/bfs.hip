@@ -518,7 +518,7 @@ __device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsign
     *a.rec = next;
 }
 
-constexpr int kUpdWords = 16;  // bitmap words per wavefront step of the update
+constexpr int kUpdWords = 8;  // bitmap words per wavefront step of the update (8 beat 4, 16, 32)
 // Groups per encoder thread of a search: 2 (segments of 1024 groups) when
 // segments of 2048 would leave fewer than two workgroups per CU, else 4.
 int search_enc_gpt(int64_t R, int64_t streams) {
@@ -537,7 +537,7 @@ __device__ __forceinline__ unsigned long long *update_sums() {
 // stages are S & ~pi_old, so f is never stored. Beside the look-back, the
 // workgroup of stream i -> j clears view (j, i) at the segment's words (the
 // view that stream decodes into) and, with the other p - 1 workgroups of
-// sender i's segment, takes the segment's 16-word steps round-robin: pi for
+// sender i's segment, takes the segment's 8-word steps round-robin: pi for
 // the next level (pi_new = S), then level and adjacency-entry count of every
 // new vertex (lane = vertex; all masked loads of a step in flight before
 // any is summed). pi is double-buffered because every receiver's workgroup
