@@ -44,8 +44,8 @@
 namespace csbfs {
 namespace {
 
-constexpr int kExpThreads = 256;
-constexpr int kPullThreads = 256;
+constexpr int kExpThreads = 512;
+constexpr int kPullThreads = 512;
 constexpr int kPullRounds = 16;  // per-lane steps (kUnroll entries each) before the wave helps
 constexpr int kEvPerLevel = 4;  // before/after the update + encode, after the decode, after the expansion
 constexpr int kPullTileDense = 64;  // bitmap words per wave tile of the dense pull
@@ -1032,10 +1032,10 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     PullArgs pb = pa;
     pa.tile_words = kPullTileDense;
     pb.tile_words = kPullTileBU;
-    // grids (multiples of the XCD count) from a sweep at scales 22 and 26:
-    // 1024 expansion workgroups (4 waves each) and 512 for the long rows beat
-    // 512-4096 and 512-2048 (scale 26: 218 -> 237 GTEPS)
-    const unsigned exp_grid = 1024, big_grid = 512;
+    // grids (multiples of the XCD count) from sweeps at scales 22 and 26:
+    // 512 expansion workgroups of 8 waves and 256 for the long rows (the
+    // same waves as 1024 and 512 of 4, which beat 512-4096 and 512-2048)
+    const unsigned exp_grid = 512, big_grid = 256;
     const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
     const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 2048);
     DirArgs da{};

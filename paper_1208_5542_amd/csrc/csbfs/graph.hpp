@@ -11,7 +11,7 @@ namespace csbfs {
 // Rows longer than kBigRow adjacency entries are expanded through the chunk
 // queue, kBigChunk entries per queue item, instead of inside their frontier
 // word's wavefront.
-constexpr int kBigRow = 64;
+constexpr int kBigRow = 128;
 constexpr int kBigChunk = 512;
 
 }  // namespace csbfs
