@@ -636,7 +636,8 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
         ea.fcount = fc;
         hipLaunchKernelGGL(bexpand_kernel, dim3(grid), dim3(kBThreads), 0, st, ea);
         CSBFS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(bexpand_big_kernel, dim3(grid), dim3(kBThreads), 0, st, ea);
+        // long rows: 1024 workgroups beat 512, 2048 and 4096 (a sweep, within 2%)
+        hipLaunchKernelGGL(bexpand_big_kernel, dim3(1024), dim3(kBThreads), 0, st, ea);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
         BUpdateArgs ua{e->vn, e->f, level, (int32_t)(j + 1), (int32_t)B, n,
