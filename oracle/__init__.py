@@ -162,6 +162,10 @@ class Alg3Result:
                             int((self.level == k).sum()))
                 for k in range(self.n_levels)]
 
+    def rank_volumes(self) -> dict:
+        """Communication volume of every processor over the whole search."""
+        return rank_volumes(self.p, self.words)
+
 
 def raw_bitmap_bytes(nbits: int) -> int:
     """Bytes of an uncompressed bitmap of nbits bits held in 64-bit words."""
@@ -194,9 +198,34 @@ def level_bytes(n: int, p: int, words, unsieved_words, frontier: int) -> dict:
         wah_unsieved = int(8 * (p - 1) * uw.sum())
     send = 8 * (words.sum(axis=1) - np.diag(words))
     recv = 8 * (words.sum(axis=0) - np.diag(words))
+    # max_rank_volume: the largest bytes sent plus received by one processor
+    # in this level alone (the whole-search volume is rank_volumes())
     return {"frontier": frontier, "raw": raw, "wah_unsieved": wah_unsieved,
             "wah_sieved": sent, "self": self_b,
             "max_rank_volume": int((send + recv).max()) if p > 1 else 0}
+
+
+def rank_volumes(p: int, words) -> dict:
+    """Communication volume of each processor (Sec. VI.A): V_i is the size of
+    every message P_i takes part in over the whole algorithm, read here as
+    the WAH bytes it sends plus the WAH bytes it receives, summed over all
+    levels, with the self stream (never communicated) left out. The volume
+    of the algorithm is V = max_i V_i.
+
+    words: [levels, p, p] stream lengths, words[k, i, j] for P_i -> P_j.
+    Returns sent[p], received[p], volume[p] (bytes) and max (bytes)."""
+    w = np.asarray(words, dtype=np.int64).reshape(-1, p, p)
+    sent = np.zeros(p, dtype=np.int64)
+    received = np.zeros(p, dtype=np.int64)
+    for k in range(w.shape[0]):
+        for i in range(p):
+            for j in range(p):
+                if i != j:
+                    sent[i] += 8 * w[k, i, j]
+                    received[j] += 8 * w[k, i, j]
+    volume = sent + received
+    return {"sent": sent.tolist(), "received": received.tolist(), "volume": volume.tolist(),
+            "max": int(volume.max()) if p > 1 else 0}
 
 
 def validate(n: int, src, dst, root: int, level, parent, ref_level=None) -> int:

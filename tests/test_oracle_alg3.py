@@ -112,5 +112,58 @@ def test_level_bytes_accounting():
         assert b["raw"] == p * (p - 1) * 8 * (R // 64)
         assert b["wah_sieved"] == 8 * sum(r.words[k, i, j] for i in range(p) for j in range(p) if i != j)
         assert b["self"] == 8 * sum(r.words[k, i, i] for i in range(p))
-        assert b["wah_sieved"] <= b["wah_unsieved"]
+        # the sieve only removes bits: every message is a subset of its
+        # sender's piece (WAH bytes need not shrink: masking a run of ones
+        # can split one fill word into several words)
+        off = ~np.eye(p, dtype=bool)
+        assert int(r.sieved_bits[k][off].sum()) <= (p - 1) * b["frontier"]
         assert b["frontier"] == int((r.level == k).sum())
+
+
+def test_rank_volume_fig2(golden):
+    """Sec. VI.A volume on the Fig. 2 example (p = 4): every stream of a
+    2-bit piece is one active word, so each processor sends and receives 3
+    words per level over levels 1..3 (hand-derived)."""
+    g = golden("fig2_example.json")
+    vd = g["volume_derived"]
+    n = g["n"]
+    src, dst = [], []
+    for u, row in enumerate(g["adjacency_rows"]):
+        for v, c in enumerate(row):
+            if c == "1" and u < v:
+                src.append(u)
+                dst.append(v)
+    # pieces of 2 bits need n % (64 p) == 0 on the GPU only; the oracle takes n = 8
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, 4, src, dst)
+    r = adj.alg3(4, V.reshape(-1), g["root"])
+    assert r.n_levels == 4
+    assert [b["max_rank_volume"] for b in r.level_bytes()] == vd["per_level_max_rank_bytes"]
+    vol = r.rank_volumes()
+    assert vol["sent"] == vd["rank_sent_bytes"]
+    assert vol["received"] == vd["rank_received_bytes"]
+    assert vol["volume"] == vd["rank_volume_bytes"]
+    assert vol["max"] == vd["volume_bytes"]
+
+
+def test_rank_volume_unequal_streams(golden):
+    """Sec. VI.A volume on a hand-derived p = 3 example whose streams have
+    unequal lengths, so sent and received bytes differ per processor."""
+    g = golden("volume_p3_example.json")
+    n, p = g["n"], g["p"]
+    adj = oracle.Adjacency(n, g["src"], g["dst"])
+    V = oracle.directory(n, p, g["src"], g["dst"])
+    r = adj.alg3(p, V.reshape(-1), g["root"])
+    assert r.n_levels == g["n_levels"]
+    for k, vs in g["levels"].items():
+        assert sorted(np.flatnonzero(r.level == int(k)).tolist()) == vs
+    assert r.words.tolist() == g["words"]
+    lb = r.level_bytes()
+    assert [b["wah_sieved"] for b in lb] == g["wah_sieved_bytes"]
+    assert [b["self"] for b in lb] == g["self_bytes"]
+    assert [b["max_rank_volume"] for b in lb] == g["per_level_max_rank_bytes"]
+    vol = r.rank_volumes()
+    assert vol["sent"] == g["rank_sent_bytes"]
+    assert vol["received"] == g["rank_received_bytes"]
+    assert vol["volume"] == g["rank_volume_bytes"]
+    assert vol["max"] == g["volume_bytes"]

@@ -118,10 +118,13 @@ def test_validator_catches_planted_mistakes(plant, bit):
     elif plant == "missing_parent":
         parent[v] = -1
     elif plant == "stray_parent":
-        unreached = [x for x in range(n) if level[x] < 0]
-        if not unreached:
-            pytest.skip("graph fully reached")
-        parent[unreached[0]] = root
+        # four isolated vertices past the tree's graph: unreached, and one
+        # of them is given a parent
+        n += 4
+        level = np.r_[level, [-1] * 4].astype(np.int32)
+        parent = np.r_[parent, [-1] * 4].astype(np.int32)
+        assert oracle.validate(n, src, dst, root, level, parent) == 0
+        parent[n - 2] = root
     elif plant == "non_edge":
         nbrs = set(dst[src == v]) | set(src[dst == v])
         others = [u for u in range(n) if level[u] == level[v] - 1 and u not in nbrs]

@@ -70,7 +70,9 @@ def test_fig2_subblock_and_directory(golden):
 
 
 def test_fig2_sieve(golden):
-    """f_2 = (1,1) is sieved to f_{2,4} = (0,1): P_4 only needs v_3 from P_2."""
+    """The sieve example of Sec. V.A on the Fig. 2 graph: of P_2's level-1
+    piece (1,1), only vertex 3 has a neighbour owned by P_4, so the message
+    from P_2 to P_4 carries (0,1)."""
     g = golden("fig2_example.json")
     n, A, src, dst = _fig2_graph(g)
     p = 4
