@@ -46,12 +46,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=64, help="timed roots")
     ap.add_argument("--warmup", type=int, default=2, help="untimed roots first")
-    ap.add_argument("--workload", default="rmat22_p4", help="rmat10_p1 | rmat22_p4 | rmat26_p8")
+    ap.add_argument("--workload", default="rmat26_p8", help="rmat10_p1 | rmat22_p4 | rmat26_p8")
+    ap.add_argument("--alpha", type=float, default=None, help="direction rule alpha (default: the library's)")
     ap.add_argument("--no-sieve", action="store_true", help="Alg. 2 messages (no directory)")
     ap.add_argument("--mode", default="auto", choices=["auto", "sparse", "dense", "bottom_up"],
                     help="evaluation of each level's product (results are identical): auto = "
                          "top-down or bottom-up per level; sparse = top-down only")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the all-cores oracle baseline (0: the host's cores, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-workload", default="rmat24_p4",
                     help="workload of the batched comparison (64 roots in one search)")
@@ -87,6 +89,31 @@ def expand_kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def expansion_bytes(s: dict, n: int, p: int) -> int:
+    """Algorithmic bytes of expanding one level. Top-down: the column ids of
+    every scanned row (4 B), the row-offset pair of every view bit (8 B), one
+    pass over the p views and one over the visited bits. Bottom-up: column
+    ids read, one row-offset pair per examined vertex, the p views, and the
+    visited and live bits scanned for candidates."""
+    from paper_1208_5542_amd import csbfs
+    if s["direction"] == csbfs.DIR_BOTTOM_UP:
+        return 4 * s["edges"] + 8 * s["pulled"] + p * n // 8 + 2 * n // 8
+    return 4 * s["edges"] + 8 * s["view_bits"] + p * n // 8 + n // 8
+
+
+def codec_bytes(s: dict, n: int, p: int) -> tuple[int, int]:
+    """Algorithmic bytes of one level's encoder and decoder. Encoder (the
+    update that forms f^k fused with the sieve and compression of its
+    messages): f_i read once per receiver and V_{j,i} once (2 p n/8), the
+    update's visited bits (3 n/8), 8 B (level, degree) per new vertex and
+    the stream words written. Decoder: the stream words read and the p
+    views written (p n/8)."""
+    words = (s["wah_sieved_bytes"] + s["self_bytes"]) // 8
+    enc = 2 * p * n // 8 + 3 * n // 8 + 8 * s["frontier"] + 8 * words
+    dec = 8 * words + p * n // 8
+    return enc, dec
+
+
 def load_traffic(workload: str):
     """HBM bytes per expansion launch from committed rocprofv3 counter runs,
     only if they were taken on the current expansion kernel source."""
@@ -101,41 +128,58 @@ def load_traffic(workload: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(n, src, dst, p, roots, budget_s):
-    """The oracle as it stands, one host thread: Alg. 3 (sieve + WAH) searches
-    on the same graph until the budget is spent (at least one root)."""
-    import numpy as np
+_CPU = {}
+
+
+def _cpu_root(root):
+    """One root through the oracle's Algorithm 3 in a forked worker (the
+    adjacency and directory are inherited from the parent, read-only)."""
+    import oracle
+    t = time.perf_counter()
+    r = _CPU["adj"].alg3(_CPU["p"], _CPU["V"], int(root), max_levels=256)
+    dt = time.perf_counter() - t
+    return int(root), dt, oracle.teps_m(_CPU["src"], _CPU["dst"], r.level)
+
+
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(n, src, dst, p, roots, workers):
+    """The oracle as it stands, on the host's cores: its serial Algorithm 3
+    (sieve + WAH streams) on the same graph and roots, one root per process,
+    `workers` processes at once (forked after the adjacency is built, so
+    they share it). The sample is one root per worker; the aggregate rate is
+    the sum of the roots' tuples over the wall time of the parallel run.
+    The one-thread rate is the harmonic mean of the same roots' own rates."""
+    import multiprocessing as mp
 
     import oracle
     t0 = time.perf_counter()
-    adj = oracle.Adjacency(n, src, dst)
-    V = oracle.directory(n, p, src, dst).reshape(-1)
+    _CPU.update(adj=oracle.Adjacency(n, src, dst), V=oracle.directory(n, p, src, dst).reshape(-1),
+                p=p, src=src, dst=dst)
     setup = time.perf_counter() - t0
-    inv, done, secs = 0.0, 0, 0.0
-    q_inv, q_done = 0.0, 0
-    for root in roots:
-        t = time.perf_counter()
-        r = adj.alg3(p, V, int(root), max_levels=256)
-        dt = time.perf_counter() - t
-        m = oracle.teps_m(src, dst, r.level)
-        inv += dt / m
-        done += 1
-        secs += dt
-        t = time.perf_counter()
-        lev = adj.bfs(int(root))
-        adj.parents_max(lev, int(root))
-        dq = time.perf_counter() - t
-        q_inv += dq / m
-        q_done += 1
-        if secs >= budget_s:
-            break
+    sample = [int(r) for r in roots[:workers]]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(processes=len(sample)) as pool:
+        res = pool.map(_cpu_root, sample, chunksize=1)
+    wall = time.perf_counter() - t0
+    _CPU.clear()
+    m_tot = sum(m for _, _, m in res)
+    one = len(res) / sum(dt / m for _, dt, m in res)
     return {
-        "value": round(done / inv / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-        "sample": f"{done} roots of the same graph through the oracle's serial Algorithm 3 "
-                  f"(queue-free level loop with sieve and WAH-64 streams), {secs:.1f} s; "
-                  f"setup (adjacency + directory) {setup:.1f} s untimed",
-        "queue_bfs_gteps": round(q_done / q_inv / 1e9, 4),
-        "queue_bfs_note": "serial FIFO-queue BFS + max-parent pass on the same roots, one thread",
+        "value": round(m_tot / wall / 1e9, 4), "unit": "GTEPS", "cores": len(sample), "kind": "oracle",
+        "sample": f"{len(sample)} roots of the same graph, one per process on {len(sample)} host cores at once, "
+                  f"each through the oracle's serial Algorithm 3 (level loop with sieve and WAH-64 streams); "
+                  f"{wall:.1f} s wall; aggregate = sum of the roots' tuples / wall time; setup (adjacency + "
+                  f"directory, {setup:.1f} s) untimed",
+        "one_thread_gteps": round(one / 1e9, 4),
+        "one_thread_note": "harmonic mean over the same roots of each root's own tuples / its own time",
+        "host_cores": host_cores(),
     }
 
 
@@ -340,6 +384,9 @@ def main():
     # gives the byte counts, the time split and the roofline
     eng = csbfs.Engine(g, max_levels=256, flags=flags)
     probe = csbfs.Engine(g, max_levels=256, flags=flags | csbfs.FLAG_TIMING)
+    if args.alpha is not None:
+        eng.set_direction(args.alpha, 24.0)
+        probe.set_direction(args.alpha, 24.0)
     level = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
     for r in roots[: args.warmup]:
@@ -369,38 +416,43 @@ def main():
     per_root = []
     for r, m in zip(roots[args.warmup:], m_of):
         res = probe.bfs(int(r), level, parent)
-        per_root.append((int(r), res.n_levels, res.stats, m))
+        per_root.append((int(r), res.n_levels, res.stats, m, probe.stream_words(res.n_levels)))
 
     # bytes and compression over every message of every timed root
     tot = {k: 0 for k in ("raw_bytes", "wah_unsieved_bytes", "wah_sieved_bytes", "self_bytes",
                           "sieved_bits", "unsieved_bits", "edges", "view_bits")}
     inv_ratio, nlev = 0.0, 0
-    exp_bytes, exp_ms, exp_launches = 0, 0.0, 0
+    # per kernel: algorithmic bytes (the formulas of expansion_bytes and
+    # codec_bytes), event time, launches; the expansion also by direction
+    kern = {k: [0, 0.0, 0] for k in ("expansion", "top_down", "bottom_up", "encode", "decode")}
     dir_count = {"top_down": 0, "bottom_up": 0}
     # the search forms f^k inside the encoder of its messages: one category
     cat_ms = {"expand": 0.0, "update_compress": 0.0, "decode": 0.0}
     R = n // p
-    for _, nl, stats, _m in per_root:
+    for _, nl, stats, _m, _w in per_root:
         for k, s in enumerate(stats):
             for key in tot:
                 tot[key] += s[key]
             if k > 0 and s["wah_sieved_bytes"] > 0:
                 inv_ratio += s["wah_sieved_bytes"] / s["raw_bytes"]
                 nlev += 1
-            # algorithmic bytes of expanding f^k. Top-down: column ids of every
-            # scanned row, the row-offset pair of every view bit, one pass over
-            # the p views and one over the visited bits. Bottom-up: column ids
-            # read, one row-offset pair per examined vertex, the p views, and
-            # the visited and live bits scanned for candidates.
-            if s["direction"] == csbfs.DIR_BOTTOM_UP:
-                exp_bytes += 4 * s["edges"] + 8 * s["pulled"] + p * n // 8 + 2 * n // 8
-                dir_count["bottom_up"] += 1
-            else:
-                exp_bytes += 4 * s["edges"] + 8 * s["view_bits"] + p * n // 8 + n // 8
-                dir_count["top_down"] += 1
-            exp_ms += s["ms_expand"]
-            exp_launches += 1
-            cat_ms["expand"] += s["ms_expand"]
+            b = expansion_bytes(s, n, p)
+            t = s["ms_expand"] + s["ms_long_rows"]
+            d = "bottom_up" if s["direction"] == csbfs.DIR_BOTTOM_UP else "top_down"
+            dir_count[d] += 1
+            for key in ("expansion", d):
+                kern[key][0] += b
+                kern[key][1] += t
+                kern[key][2] += 1
+            if k > 0:
+                eb, db = codec_bytes(s, n, p)
+                kern["encode"][0] += eb
+                kern["encode"][1] += s["ms_compress"]
+                kern["encode"][2] += 1
+                kern["decode"][0] += db
+                kern["decode"][1] += s["ms_decode"]
+                kern["decode"][2] += 1
+            cat_ms["expand"] += t
             cat_ms["update_compress"] += s["ms_update"] + s["ms_compress"]
             cat_ms["decode"] += s["ms_decode"]
     if p > 1:
@@ -408,7 +460,7 @@ def main():
         sieve_gain = tot["wah_unsieved_bytes"] / max(tot["wah_sieved_bytes"], 1)
         c_factor = inv_ratio / max(nlev, 1)
     else:  # one processor: only the self stream exists
-        raw_self = sum((len(st) - 1) * 8 * (R // 64) for _, _, st, _ in per_root)
+        raw_self = sum((len(st) - 1) * 8 * (R // 64) for _, _, st, _, _ in per_root)
         ratio = raw_self / max(tot["self_bytes"], 1)
         sieve_gain = None
         c_factor = None
@@ -417,7 +469,7 @@ def main():
     # raw bitmap, Alg. 2 its WAH stream, Alg. 3 the sieved WAH stream; a
     # sparse vector sends 8-byte ids of the piece to the p - 1 others
     by_level = {}
-    for _, _nl, stats, _m in per_root:
+    for _, _nl, stats, _m, _w in per_root:
         for k, st_ in enumerate(stats):
             if k == 0:
                 continue  # seeded, never sent
@@ -439,9 +491,24 @@ def main():
         "per_level_cheapest_total": switch_total,
         "note": "bytes sent between processors (i != j) over all timed roots; level 0 is seeded",
     } if p > 1 else None
-    achieved = exp_bytes / (exp_ms / 1e3) / 1e9 if exp_ms > 0 else 0.0
-    bpl = exp_bytes / max(exp_launches, 1)
+    def rate(key):
+        b, ms_, launches = kern[key]
+        gbs = b / (ms_ / 1e3) / 1e9 if ms_ > 0 else 0.0
+        return {"achieved": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 5),
+                "algorithmic_bytes_per_launch": round(b / max(launches, 1)),
+                "avg_launch_ms": round(ms_ / max(launches, 1), 5), "launches": launches}
+    exp = rate("expansion")
     traffic = load_traffic(wl.name)
+    # Sec. VI.A: the volume of each processor over a whole search (sent +
+    # received WAH bytes, self streams left out), max over processors,
+    # averaged over the timed roots
+    vols = []
+    for _, nl, _st, _m, words in per_root:
+        w = words[1:nl].astype(np.int64)
+        off = ~np.eye(p, dtype=bool)
+        sent = (8 * w * off).sum(axis=(0, 2))
+        recv = (8 * w * off).sum(axis=(0, 1))
+        vols.append(int((sent + recv).max()) if p > 1 else 0)
 
     out = {
         "metric": METRIC,
@@ -469,13 +536,20 @@ def main():
         "time_split_ms": {k: round(v / args.steps, 4) for k, v in cat_ms.items()},
         "levels_by_direction": dir_count,
         "mode_switch": mode_switch,
+        "volume_bytes": {"mean_over_roots": round(float(np.mean(vols)), 1), "max_over_roots": max(vols),
+                         "note": "Sec. VI.A: max over processors of the WAH bytes a processor sends plus "
+                                 "receives over one whole search"},
         "roofline": {"bound": "hbm",
-                     "kernel": "expansion step (level_kernel: top-down push or bottom-up pull; expand_big_kernel)",
-                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "kernel": "expansion step of one level: level_kernel (top-down push or bottom-up pull, "
+                               "chosen per level) + expand_big_kernel (top-down long rows); time = the two "
+                               "kernels' own HIP-event intervals on the library's stream",
+                     "achieved": exp["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp["frac"],
                      "traffic": traffic,
-                     "algorithmic_bytes_per_launch": round(bpl),
-                     "avg_launch_ms": round(exp_ms / max(exp_launches, 1), 5)},
+                     "algorithmic_bytes_per_launch": exp["algorithmic_bytes_per_launch"],
+                     "avg_launch_ms": exp["avg_launch_ms"],
+                     "by_direction": {"top_down": rate("top_down"), "bottom_up": rate("bottom_up")},
+                     "other_kernels": {"frontier_encode_kernel (update + sieve + compress)": rate("encode"),
+                                       "search_decode_kernel (decode/merge + reduction)": rate("decode")}},
         "wall_s": round(wall, 3),
     }
     if not args.no_batched:
@@ -485,12 +559,13 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_section(args)
     if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(n, src, dst, p, roots[args.warmup:], args.cpu_seconds)
+        workers = args.cpu_workers or min(16, host_cores())
+        log(f"[bench] CPU oracle baseline on {workers} processes ...")
+        out["cpu_baseline"] = cpu_baseline(n, src, dst, p, roots[args.warmup:], workers)
     if args.json_out:
         detail = dict(out)
         detail["per_root"] = [{"root": r, "levels": nl, "m": m, "ms": t, "stats": st}
-                              for (r, nl, st, m), t in zip(per_root, ms)]
+                              for (r, nl, st, m, _w), t in zip(per_root, ms)]
         with open(args.json_out, "w") as f:
             json.dump(detail, f, indent=1)
     print(json.dumps(out), flush=True)

@@ -27,8 +27,13 @@
  *   - Bit vectors are arrays of uint64 words: bit k of a vector is bit k % 64
  *     of word k / 64.
  *   - Vertex ids are int64 at the interface and must be < 2^31.
- *   - The library allocates device memory only in csbfs_graph_build and
- *     csbfs_engine_create; csbfs_bfs and the codec calls allocate nothing.
+ *   - Memory. Every device buffer can be the caller's: csbfs_layout_query
+ *     gives the exact sizes, csbfs_graph_build_into builds a graph in a
+ *     caller buffer and csbfs_bfs_ws searches in a caller workspace; neither
+ *     allocates device memory nor synchronizes anything but its own stream.
+ *     The convenience calls csbfs_graph_build and csbfs_engine_create
+ *     allocate those same buffers themselves (hipMalloc) and free them in
+ *     csbfs_graph_free and csbfs_engine_free. The codec calls allocate nothing.
  *
  * The WAH-64 stream format (Sec. IV, Table 3 and the 32-bit example in the
  * source of that table). A stream encodes N bits b[0..N) as 63-bit groups;
@@ -52,7 +57,7 @@
 extern "C" {
 #endif
 
-#define CSBFS_VERSION 10100 /* 1.1.0 */
+#define CSBFS_VERSION 10200 /* 1.2.0 */
 
 #define CSBFS_OK 0
 #define CSBFS_EINVAL (-1)    /* null pointer, bad size or bad flag */
@@ -100,7 +105,27 @@ typedef struct csbfs_graph csbfs_graph;
 int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t n_tuples, int64_t n,
                       int32_t p, void *stream, csbfs_graph **out);
 
-/* Release a graph and all its device memory. NULL is accepted. Blocking. */
+/*
+ * The same partition built in caller-owned device memory (Sec. V.A; the
+ * problem statement of Sec. II: the caller holds the graph and the search's
+ * state, the library computes). graph_mem (graph_bytes) receives the graph
+ * and must stay valid and unmodified while the handle is used; scratch
+ * (scratch_bytes) holds the build's temporaries and is free again when the
+ * call returns. Sizes come from csbfs_layout_query (same n, n_tuples, p);
+ * both buffers must start at a multiple of 256 bytes. The handle itself is
+ * small host memory; csbfs_graph_free releases it and never frees the
+ * caller's buffer. No device allocation; synchronizes `stream` only
+ * (blocking). Errors: as csbfs_graph_build, plus EINVAL (null or misaligned
+ * buffer) and ENOSPACE (a buffer smaller than the query gives).
+ */
+int csbfs_graph_build_into(const int64_t *src, const int64_t *dst, int64_t n_tuples, int64_t n, int32_t p,
+                           void *graph_mem, size_t graph_bytes, void *scratch, size_t scratch_bytes,
+                           void *stream, csbfs_graph **out);
+
+/* Release a graph handle. A graph built by csbfs_graph_build also frees its
+ * device memory (hipFree, which waits for work still using it); one built by
+ * csbfs_graph_build_into leaves the caller's buffer alone and makes no HIP
+ * call. NULL is accepted. */
 int csbfs_graph_free(csbfs_graph *g);
 
 typedef struct csbfs_graph_info {
@@ -170,22 +195,66 @@ typedef struct csbfs_engine csbfs_engine;
 #define CSBFS_FLAG_DENSE_ONLY 16u
 #define CSBFS_FLAG_BOTTOM_UP_ONLY 32u
 
+/*
+ * Parameters of one search on a caller workspace (csbfs_bfs_ws); a zeroed
+ * struct (or NULL) gives the defaults.
+ *   flags           CSBFS_FLAG_KEEP_STREAMS, NO_SIEVE and at most one of
+ *                   SPARSE_ONLY, DENSE_ONLY, BOTTOM_UP_ONLY (TIMING is an
+ *                   engine feature and is rejected here).
+ *   max_levels      levels whose counters (and, with KEEP_STREAMS, streams)
+ *                   are kept, 1..65536; 0 means 64. Deeper searches still run
+ *                   to the end; their extra levels are not reported.
+ *   alpha, beta     the direction rule of csbfs_engine_set_direction; both 0
+ *                   mean alpha = 16, beta = 24; alpha < 0 keeps every level
+ *                   top-down; beta >= 0.
+ *   segment_groups  groups of 63 bits per encoder segment: 1024 or 2048, or
+ *                   0 to choose from the sizes (same streams either way).
+ *   reserved        0.
+ */
+typedef struct csbfs_search_config {
+    uint32_t flags;
+    int32_t max_levels;
+    float alpha;
+    float beta;
+    int32_t segment_groups;
+    int32_t reserved;
+} csbfs_search_config;
+
+/* Byte sizes of the caller-owned device buffers. */
+typedef struct csbfs_sizes {
+    int64_t graph_bytes;          /* a built graph (csbfs_graph_build_into graph_mem) */
+    int64_t build_scratch_bytes;  /* temporaries of csbfs_graph_build_into */
+    int64_t workspace_bytes;      /* one search (csbfs_bfs_ws workspace) */
+    int64_t alignment;            /* every buffer starts at a multiple of this (256) */
+} csbfs_sizes;
+
+/*
+ * Exact sizes of the buffers for a graph of n vertices and n_tuples tuples
+ * on p processors, and of a search workspace for config cfg (NULL =
+ * defaults). Host arithmetic only: no device is touched. The sizes depend on
+ * (n, n_tuples, p, cfg) alone, never on the tuples themselves. Errors: EINVAL
+ * (out NULL, bad config, n_tuples < 0), ERANGE (n or p not admissible, as in
+ * csbfs_graph_build).
+ */
+int csbfs_layout_query(int64_t n, int64_t n_tuples, int32_t p, const csbfs_search_config *cfg,
+                       csbfs_sizes *out);
+
 /* Level directions reported in csbfs_level_stats.direction. */
 #define CSBFS_DIR_TOP_DOWN 0
 #define CSBFS_DIR_BOTTOM_UP 1
 #define CSBFS_DIR_DENSE 2
 
 /*
- * Allocate the workspace of Algorithm 3 for graph g: visited vector pi (two
- * copies, one per level parity; f_i and t_i are formed inside the encoder
- * and never stored), the p frontier views (p * n bits),
- * the WAH stream arena (p * p streams of floor((n/p)/63) + 1 words, times
- * max_levels with CSBFS_FLAG_KEEP_STREAMS), the expansion work queue and the
- * per-level counters for up to max_levels levels (1 <= max_levels <= 65536).
- * The graph must outlive the engine. The encoder's segment size (1024 or
- * 2048 groups of 63 bits) is chosen from n/p and p; the environment variable
- * CSBFS_ENC_GPT=2 or 4 fixes it to 1024 or 2048 (same results, other speed).
- * Blocking. Errors: EINVAL, EHIP.
+ * Allocate (hipMalloc) a search workspace of Algorithm 3 for graph g, the
+ * one csbfs_bfs_ws takes for a config of these flags and max_levels:
+ * visited vector pi (two copies, one per level parity; f_i and t_i are
+ * formed inside the encoder and never stored), the p frontier views (p * n
+ * bits), the WAH stream arena (p * p streams of floor((n/p)/63) + 1 words,
+ * times max_levels with CSBFS_FLAG_KEEP_STREAMS), the expansion work queue
+ * and the per-level counters for up to max_levels levels (1 <= max_levels
+ * <= 65536); plus a pinned two-word mailbox and, with CSBFS_FLAG_TIMING,
+ * four events per level. The graph must outlive the engine. The encoder's
+ * segment size is chosen from n/p and p. Errors: EINVAL, EHIP.
  */
 int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags,
                         csbfs_engine **out);
@@ -198,12 +267,12 @@ int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags
  * the frontier did not shrink; a
  * bottom-up search turns top-down again when |f^{k+1}| * beta < n and the
  * frontier shrank. Level 0 is top-down. alpha <= 0 keeps every level
- * top-down. Defaults: alpha = 8, beta = 24. Takes effect at the next
+ * top-down. Defaults: alpha = 16, beta = 24. Takes effect at the next
  * csbfs_bfs. Errors: EINVAL (NULL engine, beta <= 0 or a NaN).
  */
 int csbfs_engine_set_direction(csbfs_engine *e, float alpha, float beta);
 
-/* Release an engine. NULL is accepted. Blocking. */
+/* Release an engine (hipFree waits for work still using it). NULL is accepted. */
 int csbfs_engine_free(csbfs_engine *e);
 
 /* Counters of one BFS level k: the frontier f^k, its expansion, and the
@@ -223,14 +292,17 @@ typedef struct csbfs_level_stats {
     int64_t self_bytes;         /* sum over i of 8 |WAH(f_i^k . V_{i,i})| (never sent) */
     int64_t max_rank_bytes;     /* max over i of Alg. 3 bytes sent plus received by P_i */
     int64_t pulled;             /* bottom-up: unvisited vertices that scanned their rows */
-    float ms_expand;            /* expansion of f^k (every expansion kernel) (TIMING) */
+    float ms_expand;            /* expansion of f^k: csbfs_bfs, its main kernel (the push or the
+                                   pull); batched, every expansion kernel (TIMING) */
     float ms_update;            /* batched: mask, visit update and reduction; csbfs_bfs: 0,
                                    its update runs inside the encode (TIMING) */
     float ms_compress;          /* sieve + WAH encode of the f^k messages; csbfs_bfs: with
                                    the update that forms f^k (TIMING) */
     float ms_decode;            /* decode/merge of the f^k messages (TIMING) */
     int32_t direction;          /* CSBFS_DIR_* used to expand f^k */
-    int32_t reserved;
+    float ms_long_rows;         /* csbfs_bfs: the top-down long-row (chunk queue) kernel of the
+                                   expansion of f^k, and the parent pull of the dense
+                                   evaluation; 0 for batched searches (TIMING) */
 } csbfs_level_stats;
 
 /*
@@ -252,6 +324,50 @@ typedef struct csbfs_level_stats {
  */
 int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t *parent,
               csbfs_level_stats *stats, int32_t stats_cap, int32_t *n_levels, void *stream);
+
+/*
+ * One breadth-first search in a caller-owned workspace: the same search,
+ * results and statistics as csbfs_bfs (Algorithm 3; the problem statement
+ * of Sec. II), with every device buffer supplied by the caller.
+ *   g            a built graph (either build call).
+ *   cfg          search parameters (NULL = defaults); the same cfg must be
+ *                given to csbfs_layout_query and to the stream copy-outs.
+ *   level, parent, stats, stats_cap, n_levels: as csbfs_bfs.
+ *   workspace    device buffer of ws_bytes >= workspace_bytes of
+ *                csbfs_layout_query (256-byte aligned, any contents: the
+ *                search clears what it needs). It holds the search's state
+ *                and, afterwards, its streams and counters until the next
+ *                search on it. One search at a time per workspace; searches
+ *                on distinct workspaces may run concurrently on distinct
+ *                streams.
+ *   host_mailbox pinned host memory of two uint64 words (hipHostMalloc, or a
+ *                torch tensor with pin_memory=True) through which the GPU
+ *                posts each level's frontier size, or NULL: the host then
+ *                copies each level's count back after the stream drains,
+ *                which costs a round trip per level. One search at a time
+ *                per mailbox.
+ * No device allocation; synchronizes `stream` only. Blocking (the level
+ * loop reads each level's frontier size one level behind the GPU). Errors:
+ * EINVAL (null or misaligned argument, bad cfg, a mailbox that is not pinned
+ * host memory), ENOSPACE (workspace too small), ERANGE (root outside
+ * [0, n)), ECORRUPT, EHIP.
+ */
+int csbfs_bfs_ws(const csbfs_graph *g, int64_t root, const csbfs_search_config *cfg, int32_t *level,
+                 int32_t *parent, csbfs_level_stats *stats, int32_t stats_cap, int32_t *n_levels,
+                 void *workspace, size_t ws_bytes, uint64_t *host_mailbox, void *stream);
+
+/* Word counts of the streams of the last csbfs_bfs_ws search on workspace,
+ * which had n_levels levels; layout as csbfs_engine_stream_words. Blocking
+ * on `stream`. Errors: EINVAL, ENOSPACE (workspace too small for cfg). */
+int csbfs_ws_stream_words(const csbfs_graph *g, const csbfs_search_config *cfg, const void *workspace,
+                          size_t ws_bytes, int32_t n_levels, int32_t *words, int32_t cap_levels, void *stream);
+
+/* Copy the stream from P_i to P_j carrying level k of the last csbfs_bfs_ws
+ * search on workspace (cfg with CSBFS_FLAG_KEEP_STREAMS); as
+ * csbfs_engine_copy_stream. */
+int csbfs_ws_copy_stream(const csbfs_graph *g, const csbfs_search_config *cfg, const void *workspace,
+                         size_t ws_bytes, int32_t n_levels, int32_t k, int32_t i, int32_t j, uint64_t *dst,
+                         int64_t cap_words, int64_t *n_words_out, void *stream);
 
 /*
  * Word counts of the last search's streams: words host int32[cap_levels * p

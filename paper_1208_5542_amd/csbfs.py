@@ -44,10 +44,20 @@ class LevelStats(ctypes.Structure):
                 ("max_rank_bytes", ctypes.c_int64), ("pulled", ctypes.c_int64),
                 ("ms_expand", ctypes.c_float), ("ms_update", ctypes.c_float),
                 ("ms_compress", ctypes.c_float), ("ms_decode", ctypes.c_float),
-                ("direction", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("direction", ctypes.c_int32), ("ms_long_rows", ctypes.c_float)]
 
     def as_dict(self) -> dict:
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+class SearchConfig(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("max_levels", ctypes.c_int32), ("alpha", ctypes.c_float),
+                ("beta", ctypes.c_float), ("segment_groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("graph_bytes", ctypes.c_int64), ("build_scratch_bytes", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("alignment", ctypes.c_int64)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -81,6 +91,15 @@ def lib():
         "csbfs_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "csbfs_last_error": ([], ctypes.c_char_p),
         "csbfs_graph_build": ([vp, vp, i64, i64, i32, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "csbfs_graph_build_into": ([vp, vp, i64, i64, i32, vp, sz, vp, sz, vp, ctypes.POINTER(vp)],
+                                   ctypes.c_int),
+        "csbfs_layout_query": ([i64, i64, i32, ctypes.POINTER(SearchConfig), ctypes.POINTER(Sizes)],
+                               ctypes.c_int),
+        "csbfs_bfs_ws": ([vp, i64, ctypes.POINTER(SearchConfig), vp, vp, ctypes.POINTER(LevelStats), i32,
+                          ctypes.POINTER(i32), vp, sz, vp, vp], ctypes.c_int),
+        "csbfs_ws_stream_words": ([vp, ctypes.POINTER(SearchConfig), vp, sz, i32, vp, i32, vp], ctypes.c_int),
+        "csbfs_ws_copy_stream": ([vp, ctypes.POINTER(SearchConfig), vp, sz, i32, i32, i32, i32, vp, i64,
+                                  ctypes.POINTER(i64), vp], ctypes.c_int),
         "csbfs_graph_free": ([vp], ctypes.c_int),
         "csbfs_graph_get_info": ([vp, ctypes.POINTER(GraphInfo)], ctypes.c_int),
         "csbfs_graph_copy_directory": ([vp, vp, i64, vp], ctypes.c_int),
@@ -148,15 +167,49 @@ def strerror(status: int) -> str:
     return lib().csbfs_strerror(status).decode()
 
 
-class Graph:
-    """The p x p sub-block grid of an undirected graph (csbfs_graph_build)."""
+def search_config(flags: int = 0, max_levels: int = 64, alpha: float = 0.0, beta: float = 0.0,
+                  segment_groups: int = 0) -> SearchConfig:
+    return SearchConfig(flags, max_levels, alpha, beta, segment_groups, 0)
 
-    def __init__(self, src: torch.Tensor, dst: torch.Tensor, n: int, p: int, stream=None):
+
+def layout_query(n: int, n_tuples: int, p: int, config: SearchConfig | None = None) -> dict:
+    """Exact byte sizes of the caller-owned buffers (csbfs_layout_query)."""
+    out = Sizes()
+    _check(lib().csbfs_layout_query(n, n_tuples, p, None if config is None else ctypes.byref(config),
+                                    ctypes.byref(out)), "csbfs_layout_query")
+    return {f[0]: int(getattr(out, f[0])) for f in Sizes._fields_}
+
+
+def _bytes_tensor(nbytes: int) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+class Graph:
+    """The p x p sub-block grid of an undirected graph.
+
+    memory="library": csbfs_graph_build (the library allocates the graph);
+    memory="caller": csbfs_graph_build_into with torch-allocated buffers of
+    the sizes csbfs_layout_query gives (the tensor is kept as self.memory)."""
+
+    def __init__(self, src: torch.Tensor, dst: torch.Tensor, n: int, p: int, stream=None,
+                 memory: str = "library"):
         assert src.dtype == torch.int64 and dst.dtype == torch.int64 and src.shape == dst.shape
         h = ctypes.c_void_p()
-        _check(lib().csbfs_graph_build(_ptr(src), _ptr(dst), src.numel(), n, p, _stream(stream),
-                                       ctypes.byref(h)), "csbfs_graph_build")
+        self.memory = None
+        if memory == "caller":
+            sz = layout_query(n, src.numel(), p)
+            self.memory = _bytes_tensor(sz["graph_bytes"])
+            scratch = _bytes_tensor(sz["build_scratch_bytes"])
+            _check(lib().csbfs_graph_build_into(_ptr(src), _ptr(dst), src.numel(), n, p, _ptr(self.memory),
+                                                self.memory.numel(), _ptr(scratch), scratch.numel(),
+                                                _stream(stream), ctypes.byref(h)), "csbfs_graph_build_into")
+            del scratch
+        else:
+            assert memory == "library", memory
+            _check(lib().csbfs_graph_build(_ptr(src), _ptr(dst), src.numel(), n, p, _stream(stream),
+                                           ctypes.byref(h)), "csbfs_graph_build")
         self._h = h
+        self.n_tuples = int(src.numel())
         info = GraphInfo()
         _check(lib().csbfs_graph_get_info(h, ctypes.byref(info)), "csbfs_graph_get_info")
         self.info = info
@@ -272,6 +325,64 @@ class Engine:
         nw = ctypes.c_int64()
         _check(lib().csbfs_engine_copy_stream(self._h, k, i, j, _ptr(out), cap, ctypes.byref(nw),
                                               _stream(stream)), "csbfs_engine_copy_stream")
+        return out[: int(nw.value)]
+
+
+class WorkspaceSearch:
+    """Searches on one graph in a caller-owned workspace (csbfs_bfs_ws): the
+    workspace is a torch tensor of the size csbfs_layout_query gives and the
+    frontier-size mailbox a pinned host tensor; the library allocates
+    nothing."""
+
+    def __init__(self, graph: Graph, config: SearchConfig | None = None, mailbox: bool = True):
+        self.graph = graph
+        self.config = config if config is not None else search_config()
+        sz = layout_query(graph.n, graph.n_tuples, graph.p, self.config)
+        self.workspace = _bytes_tensor(sz["workspace_bytes"])
+        self.mailbox = torch.zeros(2, dtype=torch.int64, pin_memory=True) if mailbox else None
+        self.max_levels = int(self.config.max_levels) or 64
+        self._stats = (LevelStats * self.max_levels)()
+        self.last_levels = 0
+
+    def _ws(self):
+        return _ptr(self.workspace), self.workspace.numel()
+
+    def bfs(self, root: int, level: torch.Tensor | None = None, parent: torch.Tensor | None = None,
+            stream=None, with_stats: bool = True) -> BfsResult:
+        n = self.graph.n
+        if level is None:
+            level = torch.empty(n, dtype=torch.int32, device="cuda")
+        if parent is None:
+            parent = torch.empty(n, dtype=torch.int32, device="cuda")
+        nl = ctypes.c_int32()
+        cap = self.max_levels if with_stats else 0
+        ws, wsb = self._ws()
+        mb = None if self.mailbox is None else ctypes.c_void_p(self.mailbox.data_ptr())
+        _check(lib().csbfs_bfs_ws(self.graph.handle, int(root), ctypes.byref(self.config), _ptr(level),
+                                  _ptr(parent), self._stats if with_stats else None, cap, ctypes.byref(nl),
+                                  ws, wsb, mb, _stream(stream)), "csbfs_bfs_ws")
+        self.last_levels = int(nl.value)
+        stats = [self._stats[k].as_dict() for k in range(min(self.last_levels, cap))]
+        return BfsResult(level, parent, self.last_levels, stats)
+
+    def stream_words(self, n_levels: int, stream=None):
+        import numpy as np
+        p = self.graph.p
+        out = np.zeros(n_levels * p * p, dtype=np.int32)
+        ws, wsb = self._ws()
+        _check(lib().csbfs_ws_stream_words(self.graph.handle, ctypes.byref(self.config), ws, wsb,
+                                           self.last_levels, out.ctypes.data_as(ctypes.c_void_p), n_levels,
+                                           _stream(stream)), "csbfs_ws_stream_words")
+        return out.reshape(n_levels, p, p)
+
+    def stream(self, k: int, i: int, j: int, stream=None) -> torch.Tensor:
+        cap = wah_capacity(self.graph.range)
+        out = torch.zeros(cap, dtype=torch.int64, device="cuda")
+        nw = ctypes.c_int64()
+        ws, wsb = self._ws()
+        _check(lib().csbfs_ws_copy_stream(self.graph.handle, ctypes.byref(self.config), ws, wsb, self.last_levels,
+                                          k, i, j, _ptr(out), cap, ctypes.byref(nw), _stream(stream)),
+               "csbfs_ws_copy_stream")
         return out[: int(nw.value)]
 
 

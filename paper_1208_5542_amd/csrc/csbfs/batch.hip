@@ -64,17 +64,19 @@ struct BArgs {
 };
 
 // Push kBUnroll (target v, root mask m) pairs; loads first, then atomics.
+// Every load is issued unconditionally: the callers clamp the positions of
+// lanes past a row's end to its last entry (an in-bounds address), and ok
+// masks those lanes' results out.
 __device__ __forceinline__ void brelax(const BArgs &a, const int64_t (&v)[kBUnroll],
                                        const uint64_t (&m)[kBUnroll], const bool (&ok)[kBUnroll]) {
     // one 16-byte load per target: its visit mask and a (possibly stale)
     // view of its discovery mask, which only saves redundant atomics
     ulonglong2 w[kBUnroll];
 #pragma unroll
-    for (int k = 0; k < kBUnroll; ++k)
-        w[k] = ok[k] ? *reinterpret_cast<const ulonglong2 *>(a.vn + 2 * v[k]) : make_ulonglong2(~0ull, ~0ull);
+    for (int k = 0; k < kBUnroll; ++k) w[k] = *reinterpret_cast<const ulonglong2 *>(a.vn + 2 * v[k]);
 #pragma unroll
     for (int k = 0; k < kBUnroll; ++k) {
-        const uint64_t add = m[k] & ~w[k].x;
+        const uint64_t add = ok[k] ? m[k] & ~w[k].x : 0ull;
         if (add & ~w[k].y) atomicOr((unsigned long long *)(a.vn + 2 * v[k] + 1), (unsigned long long)add);
     }
 }
@@ -181,7 +183,8 @@ __global__ __launch_bounds__(kBThreads) void bexpand_kernel(BArgs a) {
                         const int32_t ex = __shfl(excl, o, 64);
                         const int32_t r0 = __shfl(rs, o, 64);
                         m[k] = (uint64_t)shfl64((int64_t)mymask, o);
-                        v[k] = vbase + (ok[k] ? colb[r0 + (e - ex)] : 0u);
+                        const int32_t ec = ok[k] ? e : total - 1;  // clamped: an entry of the last row
+                        v[k] = vbase + colb[r0 + (ec - ex)];
                     }
                     brelax(a, v, m, ok);
                 }
@@ -219,7 +222,7 @@ __global__ __launch_bounds__(kBThreads) void bexpand_big_kernel(BArgs a) {
                 for (int k = 0; k < kBUnroll; ++k) {
                     const int32_t e = e0 + 64 * k + lane;
                     ok[k] = e < it.end;
-                    v[k] = vbase + (ok[k] ? colb[e] : 0u);
+                    v[k] = vbase + colb[ok[k] ? e : it.end - 1];  // clamped to the item's last entry
                     m[k] = it.mask;
                 }
                 brelax(a, v, m, ok);

@@ -1,8 +1,9 @@
 // The level loop of Algorithm 3 (Sec. V.B) over P virtual processors on one
 // GPU. Processor i's state lives in slices of device arrays: visited bits
-// pi_i and frontier piece f_i (R bits each), the "seen" bits S_i (pi_i plus
-// the vertices discovered during the current level), and its P incoming
-// frontier pieces f_{i,j}, the "views" (bits of R_j as received from P_j).
+// pi_i (R bits), the bits N_i of the vertices discovered during the current
+// expansion (two copies by level parity: one is the frontier f_i being sent
+// while the other collects the next one), and its P incoming frontier
+// pieces f_{i,j}, the "views" (bits of R_j as received from P_j).
 // Level k (launch order: update + sieve + compress, decode + reduction,
 // expansion):
 //
@@ -12,20 +13,20 @@
 //              top-down (sparse): every set bit u of view (i, j) is a source
 //                      whose row in block (i, j) is pushed to its targets v
 //                      in R_i; an unvisited v takes u by atomicMax into
-//                      parent[v], and its first discoverer sets its S bit;
+//                      parent[v], and its first discoverer sets its N bit;
 //              bottom-up: every unvisited v of R_i reads its merged row
 //                      (global ids in decreasing order) and stops at the
 //                      first neighbour set in P_i's views: the maximum;
-//              dense:  a top-down push that only sets S bits (a bitmap small
-//                      enough to stay in L2), then every new v pulls its
-//                      parent as in bottom-up.
+//              dense:  a top-down push that only sets N bits, then every
+//                      new v pulls its parent as in bottom-up.
 //            By default each level is top-down or bottom-up: the
 //            reduction applies Beamer's rule to the frontier's size and
 //            adjacency entries and stores the direction (and the top-down
 //            tile width) on the device, where the expansion reads it.
-//   update   f_i = S_i & ~pi_i, formed while the encoder stages it (never
-//            stored); pi_i = S_i (the other parity's copy); level[v] = k;
-//            the views are cleared for this level's messages.
+//   update   f_i = N_i (the copy the last expansion filled), staged by the
+//            encoder; pi_i |= f_i; level[v] = k; the other copy of N_i
+//            (the frontier before) is cleared for the next expansion; the
+//            views are cleared for this level's messages.
 //   sieve + compress   stream i -> j = WAH-64(f_i AND V_{j,i})
 //   exchange           stream slot (i, j) is P_j's receive buffer from P_i
 //   decode/merge       view (j, i) |= WAH^-1(stream i -> j); the decode's
@@ -35,7 +36,8 @@
 // Processor i's pull reads the column of v in its block-row A_{i,*}; by the
 // symmetry of A that is the row of v in blocks (j, i), which the graph keeps
 // merged per vertex (the pull layout) next to the blocks.
-#include <cstdlib>
+#include <algorithm>
+#include <memory>
 #include <vector>
 
 #include "wah_device.hpp"
@@ -47,7 +49,8 @@ namespace {
 constexpr int kExpThreads = 512;
 constexpr int kPullThreads = 512;
 constexpr int kPullRounds = 16;  // per-lane steps (kUnroll entries each) before the wave helps
-constexpr int kEvPerLevel = 4;  // before/after the update + encode, after the decode, after the expansion
+constexpr int kEvPerLevel = 5;  // before/after the update + encode, after the decode, after the
+                                // main expansion kernel, after the long rows
 constexpr int kPullTileDense = 64;  // bitmap words per wave tile of the dense pull
 constexpr int kPullTileBU = 8;      // ... and of the bottom-up pull (many more candidates; 8 beat 2 and 4)
 constexpr int32_t kDirTD = CSBFS_DIR_TOP_DOWN, kDirBU = CSBFS_DIR_BOTTOM_UP, kDirDense = CSBFS_DIR_DENSE;
@@ -68,8 +71,8 @@ struct ExpandArgs {
     const int32_t *row_ptr;
     const int64_t *col_base;
     const uint32_t *col;
-    const uint64_t *pi;
-    uint64_t *S;
+    const uint64_t *pi;        // visited through the level being expanded
+    uint64_t *N;               // vertices discovered by this expansion (zero at its start)
     int32_t *parent;
     BigItem *queue;
     const int64_t *qoff;       // [P + 1]: processor r's chunk queue is queue[qoff[r], qoff[r+1])
@@ -86,45 +89,48 @@ struct ExpandArgs {
 
 
 constexpr int kUnroll = 2;  // independent edges in flight per lane (2 beat 4 and 8: scale 26 237 -> 253 GTEPS)
+constexpr int kTilesAhead = 4;  // view tiles whose words are loaded together
+constexpr int kBigUnroll = 2;   // edges in flight per lane in the long-row kernel
 
 // Relax kUnroll (target v, source u) pairs; every load is issued before any
 // result is used, so their latencies overlap.
 //   sparse: an unvisited v takes u by atomicMax into parent[v]; the lane
-//           that finds it still without a parent also sets its seen bit.
-//   dense:  v is only marked seen.
-template <bool kDense>
-__device__ __forceinline__ void relax_batch(const ExpandArgs &a, const int64_t (&v)[kUnroll],
-                                            const int32_t (&u)[kUnroll], const bool (&ok)[kUnroll]) {
+//           that finds it still without a parent also sets its N bit.
+//   dense:  an unvisited v is only marked in N.
+template <bool kDense, int U>
+__device__ __forceinline__ void relax_batch(const ExpandArgs &a, const int64_t (&v)[U], const int32_t (&u)[U],
+                                            const bool (&ok)[U]) {
     if (kDense) {
-        uint64_t w[kUnroll];
+        uint64_t w[U];
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k)
-            w[k] = ok[k] ? __hip_atomic_load(&a.S[v[k] >> 6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+        for (int k = 0; k < U; ++k)
+            w[k] = ok[k] ? (a.pi[v[k] >> 6] | __hip_atomic_load(&a.N[v[k] >> 6], __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT))
                          : ~0ull;
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
+        for (int k = 0; k < U; ++k) {
             const uint64_t bit = 1ull << (v[k] & 63);
-            if (!(w[k] & bit)) atomicOr((unsigned long long *)&a.S[v[k] >> 6], (unsigned long long)bit);
+            if (!(w[k] & bit)) atomicOr((unsigned long long *)&a.N[v[k] >> 6], (unsigned long long)bit);
         }
     } else {
-        uint64_t pw[kUnroll];
+        uint64_t pw[U];
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) pw[k] = ok[k] ? a.pi[v[k] >> 6] : ~0ull;
-        int32_t old[kUnroll];
+        for (int k = 0; k < U; ++k) pw[k] = ok[k] ? a.pi[v[k] >> 6] : ~0ull;
+        int32_t old[U];
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
+        for (int k = 0; k < U; ++k) {
             const bool need = !((pw[k] >> (v[k] & 63)) & 1);
             old[k] = need ? __hip_atomic_load(&a.parent[v[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                           : INT32_MAX;
         }
         // The first atomicMax on a vertex comes from a lane whose load still
-        // saw no parent: that lane also marks the vertex seen, so S & ~pi
-        // is exactly this level's new vertices.
+        // saw no parent: that lane also sets its N bit, so N is exactly this
+        // level's new vertices.
 #pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
+        for (int k = 0; k < U; ++k) {
             if (old[k] < u[k]) atomicMax(&a.parent[v[k]], u[k]);
             if (old[k] < 0)
-                atomicOr((unsigned long long *)&a.S[v[k] >> 6], (unsigned long long)(1ull << (v[k] & 63)));
+                atomicOr((unsigned long long *)&a.N[v[k] >> 6], (unsigned long long)(1ull << (v[k] & 63)));
         }
     }
 }
@@ -134,14 +140,19 @@ __device__ __forceinline__ void relax_batch(const ExpandArgs &a, const int64_t (
 // longer than kBigRow go to the chunk queue (one wave-aggregated
 // reservation); the remaining edges of the 64 sources are spread evenly over
 // the lanes, kUnroll edges per lane per step.
-template <bool kDense>
-__device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int64_t tile,
-                                            unsigned long long &edges) {
+// The view word of this lane in tile `tile` of processor r (0 past the end).
+__device__ __forceinline__ uint64_t tile_word(const ExpandArgs &a, int32_t r, int64_t tile) {
     const int lane = threadIdx.x & 63;
     const int64_t wl = tile * a.tile_words + lane;
     const bool in = lane < a.tile_words && wl < a.rank_words;
+    return in ? a.view[(int64_t)r * a.rank_words + wl] : 0;
+}
+
+template <bool kDense>
+__device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int64_t tile, uint64_t bits,
+                                            unsigned long long &edges) {
+    const int lane = threadIdx.x & 63;
     const int64_t w0 = (int64_t)r * a.rank_words + tile * a.tile_words;  // word of lane 0
-    const uint64_t bits = in ? a.view[w0 + lane] : 0;
     const int cnt = __popcll(bits);
     const int incl_b = wave_incl_scan_i32(cnt);
     const int tot_b = __shfl(incl_b, 63, 64);
@@ -214,7 +225,7 @@ __device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int6
             }
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) v[k] = vbase + c[k];
-            relax_batch<kDense>(a, v, uu, ok);
+            relax_batch<kDense, kUnroll>(a, v, uu, ok);
         }
     }
 }
@@ -230,9 +241,25 @@ __device__ __forceinline__ void expand_body(const ExpandArgs &a) {
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t ntiles = (a.rank_words + a.tile_words - 1) / a.tile_words;
     unsigned long long edges = 0;
-    for (int64_t gt = wave; gt < ntiles * a.P; gt += nwaves) {
-        const int32_t r = (int32_t)(gt / ntiles);
-        expand_tile<kDense>(a, r, gt - (int64_t)r * ntiles, edges);
+    // kTilesAhead tiles' words are loaded before any is looked at: most
+    // tiles of a small frontier are empty, and their loads then overlap
+    const int64_t total = ntiles * a.P;
+    for (int64_t gt0 = wave; gt0 < total; gt0 += nwaves * kTilesAhead) {
+        uint64_t bits[kTilesAhead];
+#pragma unroll
+        for (int k = 0; k < kTilesAhead; ++k) {
+            const int64_t gt = gt0 + k * nwaves;
+            const int32_t r = (int32_t)(gt / ntiles);
+            bits[k] = gt < total ? tile_word(a, r, gt - (int64_t)r * ntiles) : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kTilesAhead; ++k) {
+            const int64_t gt = gt0 + k * nwaves;
+            if (gt < total && __ballot(bits[k] != 0)) {
+                const int32_t r = (int32_t)(gt / ntiles);
+                expand_tile<kDense>(a, r, gt - (int64_t)r * ntiles, bits[k], edges);
+            }
+        }
     }
     // `total` is wave-uniform, so every lane holds the wave's edge count
     block_add<kExpThreads / 64>(edges, a.edges);
@@ -272,18 +299,18 @@ __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
             const int32_t j = (int32_t)(b - (int64_t)r * a.P);
             const int32_t u = (int32_t)(j * a.R + it.u_local);
             const uint32_t *colb = a.col + a.col_base[b];
-            for (int32_t e0 = it.start; e0 < it.end; e0 += 64 * kUnroll) {
-                int64_t v[kUnroll];
-                int32_t uu[kUnroll];
-                bool ok[kUnroll];
+            for (int32_t e0 = it.start; e0 < it.end; e0 += 64 * kBigUnroll) {
+                int64_t v[kBigUnroll];
+                int32_t uu[kBigUnroll];
+                bool ok[kBigUnroll];
 #pragma unroll
-                for (int k = 0; k < kUnroll; ++k) {
+                for (int k = 0; k < kBigUnroll; ++k) {
                     const int32_t e = e0 + 64 * k + lane;
                     ok[k] = e < it.end;
                     v[k] = vbase + (ok[k] ? colb[e] : 0u);
                     uu[k] = u;
                 }
-                relax_batch<kDense>(a, v, uu, ok);
+                relax_batch<kDense, kBigUnroll>(a, v, uu, ok);
             }
             edges += (unsigned long long)(it.end - it.start);
         }
@@ -292,7 +319,7 @@ __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
 }
 
 struct PullArgs {
-    uint64_t *S;
+    uint64_t *N;           // vertices discovered in this level
     const uint64_t *pi;
     const uint64_t *live;  // vertices with at least one adjacency entry
     const uint64_t *view;
@@ -316,12 +343,12 @@ struct PullArgs {
 // P_i's views (i, 0..P-1) are consecutive R-bit pieces, so together they are
 // one n-bit map indexed by the global id.
 //   dense (second half of the dense evaluation): the candidates are the
-//       vertices discovered in this level (S & ~pi); each has a frontier
+//       vertices discovered in this level (N); each has a frontier
 //       neighbour.
 //   bottom-up: the candidates are the unvisited vertices with at least one
 //       adjacency entry (~pi & live); one that finds no frontier neighbour
 //       stays unvisited. The found ones are gathered per bitmap word in LDS
-//       and set in S by the wave that owns the word.
+//       and set in N by the wave that owns the word.
 // A wavefront takes tile_words bitmap words at a time and ranks their
 // candidates, 64 at a time (lane = v). Each lane reads kUnroll entries per
 // step; lanes still searching after kPullRounds steps are finished by the
@@ -341,7 +368,7 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
         const int64_t wq = tile * tw_n + lane;
         uint64_t t = 0;
         if (lane < tw_n && wq < a.words)
-            t = kBottomUp ? (a.live[wq] & ~a.pi[wq]) : (a.S[wq] & ~a.pi[wq]);
+            t = kBottomUp ? (a.live[wq] & ~a.pi[wq]) : a.N[wq];
         const int cnt = __popcll(t);
         const int incl_b = wave_incl_scan_i32(cnt);
         const int tot_b = __shfl(incl_b, 63, 64);
@@ -433,12 +460,12 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
             }
         }
         if (kBottomUp) {
-            // this wave owns the tile's words of S: merge the found vertices
+            // this wave owns the tile's words of N: merge the found vertices
             wave_lds_sync();
             if (lane < tw_n && wq < a.words) {
                 const unsigned long long fb = found_bits[wid][lane];
                 if (fb) {
-                    a.S[wq] |= fb;
+                    a.N[wq] |= fb;
                     found_bits[wid][lane] = 0;
                 }
             }
@@ -518,6 +545,7 @@ __device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsign
     *a.rec = next;
 }
 
+constexpr int64_t kDecGridChunks = 16;  // decode workgroups per stream (each loops over chunks)
 constexpr int kUpdWords = 8;  // bitmap words per wavefront step of the update (8 beat 4, 16, 32)
 // Groups per encoder thread of a search: 2 (segments of 1024 groups) when
 // segments of 2048 would leave fewer than two workgroups per CU, else 4.
@@ -532,20 +560,21 @@ __device__ __forceinline__ unsigned long long *update_sums() {
     return sums;
 }
 
-// The update of Alg. 3 (t = S and not pi, pi = pi or t, f = t, levels of
-// the new vertices) done inside the encoder of f. The words the encoder
-// stages are S & ~pi_old, so f is never stored. Beside the look-back, the
+// The update of Alg. 3 (t = the new vertices, pi = pi or t, f = t, levels
+// of the new vertices) done inside the encoder of f. The words the encoder
+// stages are N_cur, filled by the last expansion. Beside the look-back, the
 // workgroup of stream i -> j clears view (j, i) at the segment's words (the
 // view that stream decodes into) and, with the other p - 1 workgroups of
-// sender i's segment, takes the segment's 8-word steps round-robin: pi for
-// the next level (pi_new = S), then level and adjacency-entry count of every
-// new vertex (lane = vertex; all masked loads of a step in flight before
-// any is summed). pi is double-buffered because every receiver's workgroup
-// reads pi_old while the words are being written.
+// sender i's segment, takes the segment's 8-word steps round-robin: pi |= f,
+// the other copy N_old (the previous frontier) cleared for the next
+// expansion, then level and adjacency-entry count of every new vertex (lane
+// = vertex; all masked loads of a step in flight before any is summed).
+// Each word is taken by one lane, and no workgroup of this launch reads pi
+// or N_old, so the plain read-modify-writes need no atomics.
 struct FrontierHook {
-    const uint64_t *S;
-    const uint64_t *pi_old;  // visited before level k
-    uint64_t *pi_new;        // visited through level k
+    const uint64_t *N_cur;   // f^k: vertices discovered while expanding f^(k-1)
+    uint64_t *N_old;         // f^(k-1): cleared here, refilled by the next expansion
+    uint64_t *pi;            // visited; pi |= f^k
     uint64_t *view;
     int32_t *level;
     const int32_t *deg;
@@ -556,8 +585,7 @@ struct FrontierHook {
     int32_t lvl;  // k
 
     __device__ __forceinline__ uint64_t load(const WahBatch &, int64_t, int64_t i, int64_t w) const {
-        const int64_t q = i * W + w;
-        return S[q] & ~pi_old[q];
+        return N_cur[i * W + w];
     }
     __device__ __forceinline__ void init() {
         if (threadIdx.x < 2) update_sums()[threadIdx.x] = 0;
@@ -578,9 +606,10 @@ struct FrontierHook {
             const int64_t qk = qa + lane;
             uint64_t tk = 0;
             if (lane < kUpdWords && qk < q1) {
-                const uint64_t sq = S[base + qk];
-                tk = sq & ~pi_old[base + qk];
-                pi_new[base + qk] = sq;
+                tk = N_cur[base + qk];
+                const uint64_t old = N_old[base + qk];
+                if (tk) pi[base + qk] |= tk;
+                if (old) N_old[base + qk] = 0;
                 cnt += (unsigned long long)__popcll(tk);
             }
             int32_t d[kUpdWords];
@@ -626,9 +655,10 @@ struct ReduceArgs {
     const unsigned long long *part;  // [nparts][2] sums of the update's workgroups
     int64_t nparts;
     unsigned long long *total;       // [2]: |f^k| and its adjacency entries (level counters)
-    unsigned long long *host;        // pinned [2]: the same, for the host
+    unsigned long long *host;        // pinned host word (level k << 32 | |f^k|), or null
     uint32_t *ctrs;                  // [P]: chunk-queue counts, cleared for the expansion
     int32_t P;
+    int32_t level;                   // k
     DirArgs dir;
 };
 
@@ -651,47 +681,55 @@ __global__ __launch_bounds__(kDecThreads) void search_decode_kernel(WahBatch b, 
         if (threadIdx.x == 0) {
             r.total[0] = nf;
             r.total[1] = mf;
-            r.host[0] = nf;
-            r.host[1] = mf;
+            // one 64-bit word (level tag, |f^k|) so the host sees both or neither
+            if (r.host)
+                __hip_atomic_store(r.host, ((unsigned long long)r.level << 32) | nf, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
             choose_direction(r.dir, nf, mf);
         }
     }
-    dec_scatter_body(b);
-}
-
-// Vertices with at least one adjacency entry, one bit each.
-__global__ void live_kernel(const int32_t *deg, int64_t n, uint64_t *live) {
-    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const uint64_t b = __ballot(v < n && deg[v] > 0);
-    if ((threadIdx.x & 63) == 0 && v < n) live[v >> 6] = b;
+    // the grid holds at most kDecGridChunks workgroups per stream, each
+    // taking every kDecGridChunks-th chunk up to the stream's end (a small
+    // frontier's streams are a few words: most chunk slots hold nothing)
+    const int64_t nw = b.n_words[blockIdx.y];
+    for (int64_t c = blockIdx.x; c < b.nchunk; c += gridDim.x) {
+        if (c > 0 && c * kDecChunk >= nw) break;
+        dec_scatter_body(b, c);
+    }
 }
 
 struct SeedArgs {
     int32_t *level;
     int32_t *parent;
     uint64_t *pi;
-    uint64_t *S;
+    uint64_t *N0;
+    uint64_t *N1;
     uint64_t *view;
     int64_t n;
     int64_t words;
     int64_t view_words;
-    uint32_t *zero;      // the search's counters, flags and tickets
+    uint32_t *zero;      // the search's counters and flags
     int64_t zero_words;
+    uint32_t *look;      // encoder look-back words and tickets (any contents in a new workspace)
+    int64_t look_words;
 };
 
 __global__ void seed_fill_kernel(SeedArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t top = a.n > a.view_words ? a.n : a.view_words;
     top = top > a.zero_words ? top : a.zero_words;
+    top = top > a.look_words ? top : a.look_words;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < top; k += stride) {
         if (k < a.zero_words) a.zero[k] = 0;
+        if (k < a.look_words) a.look[k] = 0;
         if (k < a.n) {
             a.level[k] = -1;
             a.parent[k] = -1;
         }
         if (k < a.words) {
             a.pi[k] = 0;
-            a.S[k] = 0;
+            a.N0[k] = 0;
+            a.N1[k] = 0;
         }
         if (k < a.view_words) a.view[k] = 0;
     }
@@ -712,7 +750,6 @@ __global__ void seed_root_kernel(SeedArgs a, int64_t root, int64_t R, int64_t W,
     a.level[root] = 0;
     a.parent[root] = (int32_t)root;
     a.pi[root >> 6] |= 1ull << (root & 63);
-    a.S[root >> 6] |= 1ull << (root & 63);
     for (int32_t i = 0; i < P; ++i) a.view[((int64_t)i * P + own) * W + (rl >> 6)] |= 1ull << (rl & 63);
     ctl0[0] = 1;
     rank0[own] = 1;
@@ -724,8 +761,12 @@ __global__ void seed_root_kernel(SeedArgs a, int64_t root, int64_t R, int64_t W,
 
 using namespace csbfs;
 
+
+namespace csbfs {
+namespace {
+
 // Per-level device counters, slot k for k < L and slot L for levels past the
-// engine's capacity (reset before each use).
+// workspace's capacity (reset before each use).
 struct LevelCounters {
     unsigned long long *ctl;     // [L+1][2]: |f^k|, sum of degrees over f^k
     unsigned long long *rank;    // [L+1][P]
@@ -737,289 +778,248 @@ struct LevelCounters {
     int32_t *dir;                // [L+1]: direction used to expand f^k
 };
 
-struct csbfs_engine {
-    const csbfs_graph *g = nullptr;
-    int device = -1;
-    int32_t L = 0;
-    uint32_t flags = 0;
-    int64_t S = 0, cap = 0, nseg = 0, nchunk = 0;
-    int enc_gpt = 4;  // groups per encoder thread (segment size)
-    uint64_t *pi[2] = {nullptr, nullptr};  // visited vertices, by level parity
-    uint64_t *seen = nullptr, *view = nullptr, *arena = nullptr;
-    unsigned long long *look = nullptr;  // encoder look-back words [S * nseg]
-    uint32_t *enc_ticket = nullptr;      // [kTicketStride * S], after look
-    size_t look_bytes = 0;
-    int64_t *chunk_groups = nullptr;
-    BigItem *queue = nullptr;
-    uint32_t *ctrs = nullptr;     // [P]: chunk-queue items pushed
-    int64_t *qoff = nullptr;      // [P + 1] chunk queue regions
-    int64_t queue_cap = 0;
-    void *counters_mem = nullptr;
-    size_t counters_bytes = 0;
-    LevelCounters lc{};
-    int32_t *status = nullptr;
-    unsigned long long *host_ctl = nullptr;  // pinned [2][2]: frontier counts, double-buffered
-    unsigned long long *host_ctl_dev = nullptr;  // its device address
-    hipEvent_t count_ev[2] = {nullptr, nullptr};
-    std::vector<hipEvent_t> events;
-    int32_t last_levels = 0;
-    uint64_t *live = nullptr;    // [n / 64]: vertices with adjacency entries
-    unsigned long long *part = nullptr;  // [S * nseg][2]: sums of the update's workgroups
-    DirState *dstate = nullptr;
-    // Beamer's parameters of the per-level direction choice, measured best
-    // on R-MAT graphs of scale 22 (4 x 4) and 26 (8 x 8)
-    float alpha = 8.0f, beta = 24.0f;
-    std::vector<void *> allocs;
+// Where every buffer of one search lives inside its workspace, and the
+// search's parameters; a function of (n, p, adjacency total, config) only.
+struct SearchLayout {
+    int64_t n, P, R, W, S, cap, nseg, nchunk, words, L, arena_slots, queue_cap;
+    int enc_gpt;  // groups per encoder thread: segments of 512 * enc_gpt groups
+    uint32_t flags;
+    float alpha, beta;
+    // byte offsets
+    int64_t pi, nb0, nb1, view, arena, look, look_bytes, chunk_groups, queue, part, dstate, counters,
+        counters_bytes, total;
 };
 
-namespace {
+// Pointers into one workspace.
+struct SearchState {
+    uint64_t *pi;    // visited
+    uint64_t *nb[2];  // new vertices, by level parity: nb[k & 1] holds f^k
+    uint64_t *view, *arena;
+    unsigned long long *look;  // look-back words [S * nseg], then tickets [kTicketStride * S]
+    uint32_t *enc_ticket;
+    int64_t *chunk_groups;
+    BigItem *queue;
+    unsigned long long *part;  // [S * nseg][2]: sums of the update's workgroups
+    DirState *dstate;
+    void *counters_mem;
+    LevelCounters lc;
+    int32_t *status;
+    uint32_t *ctrs;  // [P]: chunk-queue items pushed
+};
 
-int engine_alloc(csbfs_engine *e, void **p, size_t bytes) {
-    CSBFS_HIP(hipMalloc(p, bytes > 0 ? bytes : 1));
-    e->allocs.push_back(*p);
+constexpr uint32_t kSearchFlags = CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE | CSBFS_FLAG_SPARSE_ONLY |
+                                  CSBFS_FLAG_DENSE_ONLY | CSBFS_FLAG_BOTTOM_UP_ONLY;
+
+int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *cfg, SearchLayout *out) {
+    csbfs_search_config c{};
+    if (cfg) c = *cfg;
+    if (c.flags & ~kSearchFlags) return fail(CSBFS_EINVAL, "search config: unknown or unsupported flag");
+    const uint32_t modes = c.flags & (CSBFS_FLAG_SPARSE_ONLY | CSBFS_FLAG_DENSE_ONLY | CSBFS_FLAG_BOTTOM_UP_ONLY);
+    if (modes & (modes - 1))
+        return fail(CSBFS_EINVAL, "search config: SPARSE_ONLY, DENSE_ONLY and BOTTOM_UP_ONLY exclude each other");
+    if (c.max_levels == 0) c.max_levels = 64;
+    if (c.max_levels < 1 || c.max_levels > 65536)
+        return fail(CSBFS_EINVAL, "search config: max_levels outside [1, 65536]");
+    if (c.alpha != c.alpha || c.beta != c.beta || c.beta < 0.f)
+        return fail(CSBFS_EINVAL, "search config: alpha must be a number and beta >= 0");
+    if (c.segment_groups != 0 && c.segment_groups != 1024 && c.segment_groups != 2048)
+        return fail(CSBFS_EINVAL, "search config: segment_groups must be 0, 1024 or 2048");
+    if (c.reserved != 0) return fail(CSBFS_EINVAL, "search config: reserved must be 0");
+    SearchLayout y{};
+    y.n = n;
+    y.P = p;
+    y.R = n / p;
+    y.W = y.R / 64;
+    y.S = (int64_t)p * p;
+    y.cap = wah_cap(y.R);
+    y.enc_gpt = c.segment_groups == 1024 ? 2 : c.segment_groups == 2048 ? 4 : search_enc_gpt(y.R, y.S);
+    y.nseg = enc_segments(y.R, y.enc_gpt);
+    y.nchunk = dec_chunks(y.R);
+    y.words = n / 64;
+    y.L = c.max_levels;
+    y.arena_slots = (c.flags & CSBFS_FLAG_KEEP_STREAMS) ? y.L + 1 : 1;
+    y.queue_cap = big_items_bound(nnz);
+    y.flags = c.flags;
+    // Beamer's parameters of the per-level direction choice, measured best
+    // on R-MAT graphs of scale 22 (4 x 4) and 26 (8 x 8)
+    y.alpha = c.alpha == 0.f && c.beta == 0.f ? 16.0f : c.alpha;
+    y.beta = c.beta == 0.f ? 24.0f : c.beta;
+    int64_t o = 0;
+    auto take = [&o](int64_t bytes) {
+        const int64_t at = o;
+        o += align_up(bytes > 0 ? bytes : 1);
+        return at;
+    };
+    y.pi = take(8 * y.words);
+    y.nb0 = take(8 * y.words);
+    y.nb1 = take(8 * y.words);
+    y.view = take(8 * y.P * y.words);
+    y.arena = take(8 * y.S * y.cap * y.arena_slots);
+    y.look_bytes = 8 * y.S * y.nseg + 4 * kTicketStride * y.S;
+    y.look = take(y.look_bytes);
+    y.chunk_groups = take(8 * y.S * y.nchunk);
+    y.queue = take((int64_t)sizeof(BigItem) * y.queue_cap);
+    y.part = take(16 * y.S * y.nseg);
+    y.dstate = take((int64_t)sizeof(DirState));
+    // everything a search starts from zero, in one block the seed clears:
+    // per-level counters, then the status flag and the queue counts
+    const int64_t slots = y.L + 1;
+    y.counters_bytes = 8 * slots * (2 + y.P + 1 + 1 + y.S + y.P) + 8 * slots * y.S + 4 * slots + 4 * (2 + y.P);
+    y.counters_bytes = (y.counters_bytes + 3) / 4 * 4;
+    y.counters = take(y.counters_bytes);
+    y.total = o;
+    *out = y;
     return CSBFS_OK;
 }
 
-void engine_release(csbfs_engine *e) {
-    (void)hipDeviceSynchronize();
-    for (void *p : e->allocs) (void)hipFree(p);
-    e->allocs.clear();
-    if (e->host_ctl) (void)hipHostFree(e->host_ctl);
-    for (hipEvent_t ev : e->count_ev)
-        if (ev) (void)hipEventDestroy(ev);
-    for (hipEvent_t ev : e->events)
-        if (ev) (void)hipEventDestroy(ev);
-    e->events.clear();
-    delete e;
+SearchState bind_workspace(const SearchLayout &y, void *ws) {
+    char *b = (char *)ws;
+    SearchState w{};
+    w.pi = (uint64_t *)(b + y.pi);
+    w.nb[0] = (uint64_t *)(b + y.nb0);
+    w.nb[1] = (uint64_t *)(b + y.nb1);
+    w.view = (uint64_t *)(b + y.view);
+    w.arena = (uint64_t *)(b + y.arena);
+    w.look = (unsigned long long *)(b + y.look);
+    w.enc_ticket = reinterpret_cast<uint32_t *>(w.look + y.S * y.nseg);
+    w.chunk_groups = (int64_t *)(b + y.chunk_groups);
+    w.queue = (BigItem *)(b + y.queue);
+    w.part = (unsigned long long *)(b + y.part);
+    w.dstate = (DirState *)(b + y.dstate);
+    w.counters_mem = b + y.counters;
+    const int64_t slots = y.L + 1, P = y.P, S = y.S;
+    unsigned long long *c = (unsigned long long *)w.counters_mem;
+    w.lc.ctl = c;
+    c += slots * 2;
+    w.lc.rank = c;
+    c += slots * P;
+    w.lc.edges = c;
+    c += slots;
+    w.lc.pulled = c;
+    c += slots;
+    w.lc.sbits = c;
+    c += slots * S;
+    w.lc.uwords = c;
+    c += slots * P;
+    w.lc.words = (int64_t *)c;
+    w.lc.dir = (int32_t *)(w.lc.words + slots * S);
+    w.status = w.lc.dir + slots;
+    w.ctrs = reinterpret_cast<uint32_t *>(w.status + 1);
+    return w;
 }
 
-}  // namespace
+inline int64_t slot_of(const SearchLayout &y, int64_t k) { return k < y.L ? k : y.L; }
 
-extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags,
-                                   csbfs_engine **out) {
-    if (!out) return fail(CSBFS_EINVAL, "csbfs_engine_create: out is NULL");
-    *out = nullptr;
-    if (!g) return fail(CSBFS_EINVAL, "csbfs_engine_create: graph is NULL");
-    if (max_levels < 1 || max_levels > 65536)
-        return fail(CSBFS_EINVAL, "csbfs_engine_create: max_levels outside [1, 65536]");
-    if (flags & ~(CSBFS_FLAG_TIMING | CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE |
-                  CSBFS_FLAG_SPARSE_ONLY | CSBFS_FLAG_DENSE_ONLY | CSBFS_FLAG_BOTTOM_UP_ONLY))
-        return fail(CSBFS_EINVAL, "csbfs_engine_create: unknown flag");
-    const uint32_t modes = flags & (CSBFS_FLAG_SPARSE_ONLY | CSBFS_FLAG_DENSE_ONLY | CSBFS_FLAG_BOTTOM_UP_ONLY);
-    if (modes & (modes - 1))
-        return fail(CSBFS_EINVAL, "csbfs_engine_create: SPARSE_ONLY, DENSE_ONLY and BOTTOM_UP_ONLY exclude each other");
-    int rc = graph_device_check(g);
-    if (rc) return rc;
-    csbfs_engine *e = new csbfs_engine();
-    e->g = g;
-    e->device = g->device;
-    e->L = max_levels;
-    e->flags = flags;
-    const int64_t P = g->P, n = g->n;
-    e->S = P * P;
-    e->cap = wah_cap(g->R);
-    e->enc_gpt = search_enc_gpt(g->R, e->S);
-    if (const char *ev = std::getenv("CSBFS_ENC_GPT")) {  // fixed segment size (tests, tuning)
-        if (ev[0] == '2' && ev[1] == 0) e->enc_gpt = 2;
-        if (ev[0] == '4' && ev[1] == 0) e->enc_gpt = 4;
-    }
-    e->nseg = enc_segments(g->R, e->enc_gpt);
-    e->nchunk = dec_chunks(g->R);
-    const int64_t words = n / 64;
-    const int64_t arena_slots = (flags & CSBFS_FLAG_KEEP_STREAMS) ? (int64_t)max_levels + 1 : 1;
-    std::vector<int64_t> qoff(P + 1, 0);
-    for (int64_t r = 0; r < P; ++r) qoff[r + 1] = qoff[r] + g->big_items[r];
-    e->queue_cap = qoff[P] > 0 ? qoff[P] : 1;
-#define ALLOC(ptr, bytes)                                                  \
-    do {                                                                   \
-        void *_p = nullptr;                                                \
-        int _rc = engine_alloc(e, &_p, (bytes));                           \
-        if (_rc) {                                                         \
-            engine_release(e);                                             \
-            return _rc;                                                    \
-        }                                                                  \
-        ptr = reinterpret_cast<decltype(ptr)>(_p);                         \
-    } while (0)
-    ALLOC(e->pi[0], sizeof(uint64_t) * words);
-    ALLOC(e->pi[1], sizeof(uint64_t) * words);
-    ALLOC(e->seen, sizeof(uint64_t) * words);
-    ALLOC(e->view, sizeof(uint64_t) * P * words);
-    ALLOC(e->arena, sizeof(uint64_t) * e->S * e->cap * arena_slots);
-    // encoder look-back words, then its tickets: zero before the first encode
-    e->look_bytes = sizeof(unsigned long long) * e->S * e->nseg + sizeof(uint32_t) * kTicketStride * e->S;
-    ALLOC(e->look, e->look_bytes);
-    e->enc_ticket = reinterpret_cast<uint32_t *>(e->look + e->S * e->nseg);
-    ALLOC(e->chunk_groups, sizeof(int64_t) * e->S * e->nchunk);
-    ALLOC(e->queue, sizeof(BigItem) * e->queue_cap);
-    ALLOC(e->qoff, sizeof(int64_t) * (P + 1));
-    ALLOC(e->live, sizeof(uint64_t) * words);
-    ALLOC(e->part, sizeof(unsigned long long) * 2 * e->S * e->nseg);
-    ALLOC(e->dstate, sizeof(DirState));
-    // everything a search starts from zero, in one block the seed clears:
-    // per-level counters, then the status flag, queue counts and update ticket
-    const int64_t slots = (int64_t)max_levels + 1;
-    const size_t cnt_bytes = sizeof(unsigned long long) * slots * (2 + P + 1 + 1 + e->S + P) +
-                             sizeof(int64_t) * slots * e->S + sizeof(int32_t) * slots +
-                             sizeof(int32_t) * (2 + P);
-    ALLOC(e->counters_mem, cnt_bytes);
-#undef ALLOC
-    e->counters_bytes = cnt_bytes;
-    const hipError_t zerr = hipMemset(e->look, 0, e->look_bytes);
-    if (zerr != hipSuccess) {
-        engine_release(e);
-        return hip_fail(zerr, "hipMemset(look)", __FILE__, __LINE__);
-    }
-    unsigned long long *c = (unsigned long long *)e->counters_mem;
-    e->lc.ctl = c;
-    c += slots * 2;
-    e->lc.rank = c;
-    c += slots * P;
-    e->lc.edges = c;
-    c += slots;
-    e->lc.pulled = c;
-    c += slots;
-    e->lc.sbits = c;
-    c += slots * e->S;
-    e->lc.uwords = c;
-    c += slots * P;
-    e->lc.words = (int64_t *)c;
-    e->lc.dir = (int32_t *)(e->lc.words + slots * e->S);
-    e->status = e->lc.dir + slots;
-    e->ctrs = reinterpret_cast<uint32_t *>(e->status + 1);
-    hipError_t herr = hipMemcpy(e->qoff, qoff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice);
-    if (herr != hipSuccess) {
-        engine_release(e);
-        return hip_fail(herr, "hipMemcpy(qoff)", __FILE__, __LINE__);
-    }
-    hipLaunchKernelGGL(live_kernel, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, 0, g->deg, n, e->live);
-    herr = hipGetLastError();
-    if (herr == hipSuccess) herr = hipDeviceSynchronize();
-    if (herr != hipSuccess) {
-        engine_release(e);
-        return hip_fail(herr, "live_kernel", __FILE__, __LINE__);
-    }
-    herr = hipHostMalloc((void **)&e->host_ctl, 4 * sizeof(unsigned long long));
-    if (herr != hipSuccess) {
-        e->host_ctl = nullptr;
-        engine_release(e);
-        return hip_fail(herr, "hipHostMalloc", __FILE__, __LINE__);
-    }
-    herr = hipHostGetDevicePointer((void **)&e->host_ctl_dev, e->host_ctl, 0);
-    if (herr != hipSuccess) {
-        engine_release(e);
-        return hip_fail(herr, "hipHostGetDevicePointer", __FILE__, __LINE__);
-    }
-    for (auto &ev : e->count_ev) {
-        herr = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (herr != hipSuccess) {
-            ev = nullptr;
-            engine_release(e);
-            return hip_fail(herr, "hipEventCreate", __FILE__, __LINE__);
-        }
-    }
-    if (flags & CSBFS_FLAG_TIMING) {
-        e->events.assign((size_t)max_levels * kEvPerLevel, nullptr);
-        for (auto &ev : e->events) {
-            herr = hipEventCreate(&ev);
-            if (herr != hipSuccess) {
-                ev = nullptr;
-                engine_release(e);
-                return hip_fail(herr, "hipEventCreate", __FILE__, __LINE__);
+int reset_overflow_slot(const SearchLayout &y, const SearchState &w, hipStream_t st) {
+    const int64_t L = y.L, P = y.P, S = y.S;
+    CSBFS_HIP(hipMemsetAsync(w.lc.ctl + 2 * L, 0, 2 * sizeof(unsigned long long), st));
+    CSBFS_HIP(hipMemsetAsync(w.lc.rank + L * P, 0, sizeof(unsigned long long) * P, st));
+    CSBFS_HIP(hipMemsetAsync(w.lc.edges + L, 0, sizeof(unsigned long long), st));
+    CSBFS_HIP(hipMemsetAsync(w.lc.pulled + L, 0, sizeof(unsigned long long), st));
+    CSBFS_HIP(hipMemsetAsync(w.lc.sbits + L * S, 0, sizeof(unsigned long long) * S, st));
+    CSBFS_HIP(hipMemsetAsync(w.lc.uwords + L * P, 0, sizeof(unsigned long long) * P, st));
+    return CSBFS_OK;
+}
+
+// Host side of the frontier-size readback. With a pinned mailbox the decode
+// of level k stores (k << 32 | |f^k|) in word k & 1 and the host polls it;
+// without one the host copies the level's counter back after the stream has
+// drained (one round trip per level).
+struct Mailbox {
+    volatile unsigned long long *host = nullptr;  // pinned, two words, or null
+    unsigned long long *dev = nullptr;            // its device address
+};
+
+int wait_count(const Mailbox &mb, const SearchLayout &y, const SearchState &w, int64_t k, hipStream_t st,
+               unsigned long long *cnt) {
+    if (mb.host) {
+        const unsigned long long want = (unsigned long long)k & 0xffffffffull;
+        uint64_t spins = 0;
+        for (;;) {
+            const unsigned long long v = mb.host[k & 1];
+            if ((v >> 32) == want) {
+                *cnt = v & 0xffffffffull;
+                return CSBFS_OK;
+            }
+            if ((++spins & 0x3ff) == 0) {
+                // a failed launch never writes the word: ask the stream
+                const hipError_t q = hipStreamQuery(st);
+                if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(q, "search stream", __FILE__, __LINE__);
+                if (q == hipSuccess) {
+                    // the stream drained: the word must be there now
+                    const unsigned long long v2 = mb.host[k & 1];
+                    if ((v2 >> 32) != want)
+                        return fail(CSBFS_ECORRUPT, "csbfs_bfs: frontier count of a level never arrived");
+                    *cnt = v2 & 0xffffffffull;
+                    return CSBFS_OK;
+                }
             }
         }
     }
-    *out = e;
+    unsigned long long v = 0;
+    CSBFS_HIP(hipMemcpyAsync(&v, w.lc.ctl + 2 * slot_of(y, k), sizeof(v), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    *cnt = v;
     return CSBFS_OK;
 }
 
-extern "C" int csbfs_engine_set_direction(csbfs_engine *e, float alpha, float beta) {
-    if (!e) return fail(CSBFS_EINVAL, "csbfs_engine_set_direction: engine is NULL");
-    if (!(beta > 0.f) || alpha != alpha)
-        return fail(CSBFS_EINVAL, "csbfs_engine_set_direction: beta must be > 0 and alpha a number");
-    e->alpha = alpha;
-    e->beta = beta;
-    return CSBFS_OK;
-}
+constexpr int kEvPerLevel2 = kEvPerLevel;
 
-extern "C" int csbfs_engine_free(csbfs_engine *e) {
-    if (!e) return CSBFS_OK;
-    engine_release(e);
-    return CSBFS_OK;
-}
-
-namespace {
-
-inline int64_t slot_of(const csbfs_engine *e, int64_t k) { return k < e->L ? k : e->L; }
-
-int reset_overflow_slot(csbfs_engine *e, hipStream_t st) {
-    const int64_t L = e->L, P = e->g->P, S = e->S;
-    CSBFS_HIP(hipMemsetAsync(e->lc.ctl + 2 * L, 0, 2 * sizeof(unsigned long long), st));
-    CSBFS_HIP(hipMemsetAsync(e->lc.rank + L * P, 0, sizeof(unsigned long long) * P, st));
-    CSBFS_HIP(hipMemsetAsync(e->lc.edges + L, 0, sizeof(unsigned long long), st));
-    CSBFS_HIP(hipMemsetAsync(e->lc.pulled + L, 0, sizeof(unsigned long long), st));
-    CSBFS_HIP(hipMemsetAsync(e->lc.sbits + L * S, 0, sizeof(unsigned long long) * S, st));
-    CSBFS_HIP(hipMemsetAsync(e->lc.uwords + L * P, 0, sizeof(unsigned long long) * P, st));
-    return CSBFS_OK;
-}
-
-}  // namespace
-
-extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t *parent,
-                         csbfs_level_stats *stats, int32_t stats_cap, int32_t *n_levels,
-                         void *stream) {
-    if (!e || !level || !parent || !n_levels || stats_cap < 0 || (stats_cap > 0 && !stats))
-        return fail(CSBFS_EINVAL, "csbfs_bfs: null argument or negative stats_cap");
-    const csbfs_graph *g = e->g;
-    if (root < 0 || root >= g->n) return fail(CSBFS_ERANGE, "csbfs_bfs: root outside [0, n)");
-    int rc = graph_device_check(g);
-    if (rc) return rc;
-    hipStream_t st = as_stream(stream);
-    const int64_t P = g->P, n = g->n, R = g->R, W = g->W, S = e->S;
+// One search from root on workspace state w (Algorithm 3 level loop).
+int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w, int64_t root, int32_t *level,
+               int32_t *parent, csbfs_level_stats *stats, int32_t stats_cap, int32_t *n_levels, const Mailbox &mb,
+               hipEvent_t *events, hipStream_t st) {
+    const int64_t P = g->P, n = g->n, R = g->R, W = g->W, S = y.S;
     const int64_t words = n / 64, view_words = P * words;
-    const bool timing = (e->flags & CSBFS_FLAG_TIMING) != 0;
-    const bool keep = (e->flags & CSBFS_FLAG_KEEP_STREAMS) != 0;
+    const bool timing = events != nullptr;
+    const bool keep = (y.flags & CSBFS_FLAG_KEEP_STREAMS) != 0;
 
     // evaluation of the product: dense, or top-down / bottom-up per level
     // (forced by a flag, or chosen on the device after every update)
-    const bool dense = (e->flags & CSBFS_FLAG_DENSE_ONLY) != 0;
-    const bool td_only = (e->flags & CSBFS_FLAG_SPARSE_ONLY) != 0 || (!dense && !(e->alpha > 0.f) &&
-                                                                      !(e->flags & CSBFS_FLAG_BOTTOM_UP_ONLY));
-    const bool bu_only = (e->flags & CSBFS_FLAG_BOTTOM_UP_ONLY) != 0;
+    const bool dense = (y.flags & CSBFS_FLAG_DENSE_ONLY) != 0;
+    const bool td_only = (y.flags & CSBFS_FLAG_SPARSE_ONLY) != 0 ||
+                         (!dense && !(y.alpha > 0.f) && !(y.flags & CSBFS_FLAG_BOTTOM_UP_ONLY));
+    const bool bu_only = (y.flags & CSBFS_FLAG_BOTTOM_UP_ONLY) != 0;
     const int32_t force = dense ? kDirDense : td_only ? kDirTD : bu_only ? kDirBU : -1;
     const int32_t dir0 = dense ? kDirDense : bu_only ? kDirBU : kDirTD;
 
-    // a0: seed
-    SeedArgs sa{level, parent, e->pi[0], e->seen, e->view, n, words, view_words,
-                (uint32_t *)e->counters_mem, (int64_t)(e->counters_bytes / sizeof(uint32_t))};
-    const int64_t fill_items = n > view_words ? n : view_words;
+    if (mb.host) {
+        mb.host[0] = 0;  // level tags start at 1
+        mb.host[1] = 0;
+    }
+    // a0: seed (also clears the counters and the encoder's look-back state)
+    SeedArgs sa{level, parent, w.pi, w.nb[0], w.nb[1], w.view, n, words, view_words,
+                (uint32_t *)w.counters_mem, y.counters_bytes / 4, (uint32_t *)w.look, y.look_bytes / 4};
+    int64_t fill_items = n > view_words ? n : view_words;
+    fill_items = fill_items > y.look_bytes / 4 ? fill_items : y.look_bytes / 4;
     hipLaunchKernelGGL(seed_fill_kernel, dim3(grid_for(fill_items, 256, 8192)), dim3(256), 0, st, sa);
     CSBFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(seed_root_kernel, dim3(1), dim3(1), 0, st, sa, root, R, W, (int32_t)P,
-                       e->lc.ctl, e->lc.rank, (const int32_t *)g->deg, e->dstate, e->lc.dir, dir0);
+    hipLaunchKernelGGL(seed_root_kernel, dim3(1), dim3(1), 0, st, sa, root, R, W, (int32_t)P, w.lc.ctl, w.lc.rank,
+                       (const int32_t *)g->deg, w.dstate, w.lc.dir, dir0);
     CSBFS_HIP(hipGetLastError());
 
     ExpandArgs ea{};
-    ea.view = e->view;
+    ea.view = w.view;
     ea.rank_words = P * W;
     ea.row_ptr = g->row_ptr;
     ea.col_base = g->col_base;
     ea.col = g->col;
-    ea.S = e->seen;
+    ea.pi = w.pi;
     ea.parent = parent;
-    ea.queue = e->queue;
-    ea.qoff = e->qoff;
-    ea.queue_count = e->ctrs;
+    ea.queue = w.queue;
+    ea.qoff = g->qoff;
+    ea.queue_count = w.ctrs;
     ea.R = R;
     ea.W = W;
     ea.P = (int32_t)P;
-    ea.status = e->status;
-    ea.dir = &e->dstate->cur;
-    ea.tile = &e->dstate->tile;
+    ea.status = w.status;
+    ea.dir = &w.dstate->cur;
+    ea.tile = &w.dstate->tile;
     ea.tile_words = 64;
     PullArgs pa{};
-    pa.S = e->seen;
-    pa.live = e->live;
-    pa.view = e->view;
+    pa.pi = w.pi;
+    pa.live = g->live;
+    pa.view = w.view;
     pa.pull_off = g->pull_off;
     pa.pull_col = g->pull_col;
     pa.parent = parent;
@@ -1027,8 +1027,8 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     pa.R = R;
     pa.W = W;
     pa.P = (int32_t)P;
-    pa.status = e->status;
-    pa.dir = &e->dstate->cur;
+    pa.status = w.status;
+    pa.dir = &w.dstate->cur;
     PullArgs pb = pa;
     pa.tile_words = kPullTileDense;
     pb.tile_words = kPullTileBU;
@@ -1039,80 +1039,81 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
     const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 2048);
     DirArgs da{};
-    da.st = e->dstate;
+    da.st = w.dstate;
     da.n = n;
     da.nnz = g->nnz;
-    da.alpha = e->alpha;
-    da.beta = e->beta;
+    da.alpha = y.alpha;
+    da.beta = y.beta;
     da.force = force;
 
     WahBatch wb{};  // the words come from FrontierHook, not from a bits buffer
-    wb.mask_base = (e->flags & CSBFS_FLAG_NO_SIEVE) ? nullptr : g->dir;
+    wb.mask_base = (y.flags & CSBFS_FLAG_NO_SIEVE) ? nullptr : g->dir;
     wb.nbits = R;
     wb.words_per_piece = W;
-    wb.cap = e->cap;
+    wb.cap = y.cap;
     wb.P = (int32_t)P;
-    wb.look = e->look;
-    wb.ticket = e->enc_ticket;
-    wb.nseg = e->nseg;
-    wb.chunk_groups = e->chunk_groups;
-    wb.nchunk = e->nchunk;
+    wb.look = w.look;
+    wb.ticket = w.enc_ticket;
+    wb.nseg = y.nseg;
+    wb.chunk_groups = w.chunk_groups;
+    wb.nchunk = y.nchunk;
     wb.chunk_starts = 1;  // the decode reads the chunk starts the encode records
-    wb.dst_base = e->view;
-    wb.status = e->status;
-    const dim3 enc_grid((unsigned)e->nseg, (unsigned)S), dec_grid((unsigned)e->nchunk, (unsigned)S);
+    wb.dst_base = w.view;
+    wb.status = w.status;
+    const dim3 enc_grid((unsigned)y.nseg, (unsigned)S),
+        dec_grid((unsigned)std::min<int64_t>(y.nchunk, kDecGridChunks), (unsigned)S);
 
     // Iteration j: for j >= 1 the update that forms f^j together with the
     // sieve and compression of its messages, then their decode into the views
-    // (whose first workgroup reduces |f^j|, writes it to host slot j & 1 and
-    // chooses the direction); then the expansion of f^j. pi[j & 1] holds the
-    // vertices visited through level j.
+    // (whose first workgroup reduces |f^j|, posts it for the host and
+    // chooses the direction); then the expansion of f^j, which collects the
+    // vertices of level j + 1 in nb[(j + 1) & 1]. pi holds the vertices
+    // visited through level j once the update of iteration j is done.
     auto enqueue_iter = [&](int64_t j) -> int {
-        const int64_t sj = slot_of(e, j);
-        if (j >= e->L) {
-            const int r2 = reset_overflow_slot(e, st);
+        const int64_t sj = slot_of(y, j);
+        if (j >= y.L) {
+            const int r2 = reset_overflow_slot(y, w, st);
             if (r2) return r2;
         }
-        hipEvent_t *ev = (timing && j < e->L) ? &e->events[(size_t)j * kEvPerLevel] : nullptr;
-        uint64_t *pi_j = e->pi[j & 1];
+        hipEvent_t *ev = (timing && j < y.L) ? &events[(size_t)j * kEvPerLevel2] : nullptr;
         if (ev) CSBFS_HIP(hipEventRecord(ev[0], st));
         if (j >= 1) {
             // a2 + a4 + a5: t = S & ~pi, levels, sieve and compress every stream i -> j
             const int64_t arena_slot = keep ? sj : 0;
-            wb.out_base = e->arena + arena_slot * S * e->cap;
-            wb.n_words = e->lc.words + sj * S;
-            wb.stat_sieved_bits = e->lc.sbits + sj * S;
-            wb.stat_unsieved_words = e->lc.uwords + sj * P;
-            FrontierHook fh{e->seen, e->pi[(j + 1) & 1], pi_j, e->view, level, g->deg, e->part, W,
-                            (int64_t)kEncThreads * e->enc_gpt * kGroupBits / 64, (int32_t)P, (int32_t)j};
-            if (e->enc_gpt == 2)
+            wb.out_base = w.arena + arena_slot * S * y.cap;
+            wb.n_words = w.lc.words + sj * S;
+            wb.stat_sieved_bits = w.lc.sbits + sj * S;
+            wb.stat_unsieved_words = w.lc.uwords + sj * P;
+            FrontierHook fh{w.nb[j & 1], w.nb[(j + 1) & 1], w.pi, w.view, level, g->deg, w.part, W,
+                            (int64_t)kEncThreads * y.enc_gpt * kGroupBits / 64, (int32_t)P, (int32_t)j};
+            if (y.enc_gpt == 2)
                 hipLaunchKernelGGL(frontier_encode_kernel<2>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
-                                   (const DirState *)e->dstate);
+                                   (const DirState *)w.dstate);
             else
                 hipLaunchKernelGGL(frontier_encode_kernel<4>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
-                                   (const DirState *)e->dstate);
+                                   (const DirState *)w.dstate);
             CSBFS_HIP(hipGetLastError());
             if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
             // a6: the stream slots are the receive buffers; a7: decode into the
             // views; a3: reduction of |f^j|, direction of its expansion
-            da.rec = e->lc.dir + sj;
-            ReduceArgs ra{e->part, S * e->nseg, e->lc.ctl + 2 * sj, e->host_ctl_dev + 2 * (j & 1), e->ctrs,
-                          (int32_t)P, da};
+            da.rec = w.lc.dir + sj;
+            ReduceArgs ra{w.part, S * y.nseg, w.lc.ctl + 2 * sj, mb.dev ? mb.dev + (j & 1) : nullptr, w.ctrs,
+                          (int32_t)P, (int32_t)j, da};
             hipLaunchKernelGGL(search_decode_kernel, dec_grid, dim3(kDecThreads), 0, st, wb, ra);
             CSBFS_HIP(hipGetLastError());
-            CSBFS_HIP(hipEventRecord(e->count_ev[j & 1], st));
         } else if (ev) {
             CSBFS_HIP(hipEventRecord(ev[1], st));
         }
         if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
-        ea.pi = pi_j;
-        pa.pi = pi_j;
-        pb.pi = pi_j;
+        ea.N = w.nb[(j + 1) & 1];
+        pa.N = w.nb[(j + 1) & 1];
+        pb.N = w.nb[(j + 1) & 1];
         // a1: expand f^j (tile width and direction chosen on the device)
-        ea.edges = e->lc.edges + sj;
+        ea.edges = w.lc.edges + sj;
         if (dense) {
             hipLaunchKernelGGL(expand_kernel<true>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
             CSBFS_HIP(hipGetLastError());
+            if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
             hipLaunchKernelGGL(expand_big_kernel<true>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
             CSBFS_HIP(hipGetLastError());
             hipLaunchKernelGGL(pull_kernel<false>, dim3(pull_grid), dim3(kPullThreads), 0, st, pa);
@@ -1120,33 +1121,36 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         } else if (td_only) {
             hipLaunchKernelGGL(expand_kernel<false>, dim3(exp_grid), dim3(kExpThreads), 0, st, ea);
             CSBFS_HIP(hipGetLastError());
+            if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
             hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
             CSBFS_HIP(hipGetLastError());
         } else {
-            pb.edges = e->lc.edges + sj;
-            pb.pulled = e->lc.pulled + sj;
+            pb.edges = w.lc.edges + sj;
+            pb.pulled = w.lc.pulled + sj;
             if (bu_only) {
                 hipLaunchKernelGGL(pull_kernel<true>, dim3(bu_grid), dim3(kPullThreads), 0, st, pb);
                 CSBFS_HIP(hipGetLastError());
+                if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
             } else {
                 // one launch: the push or the pull, as the level's direction
                 // says; the long-row pass returns at once on bottom-up levels
                 hipLaunchKernelGGL(level_kernel, dim3(exp_grid), dim3(kExpThreads), 0, st, ea, pb);
                 CSBFS_HIP(hipGetLastError());
+                if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
                 hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
                 CSBFS_HIP(hipGetLastError());
             }
         }
-        if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
+        if (ev) CSBFS_HIP(hipEventRecord(ev[4], st));
         return CSBFS_OK;
     };
 
-    // The host reads |f^k| (written by the decode of level k) while the
+    // The host reads |f^k| (posted by the decode of level k) while the
     // expansion of level k and iteration k + 1 are already queued. When f^k
     // is empty the decode chose the idle direction: the expansion of level k
     // and every kernel of iteration k + 1 return at once, and their counters
     // lie past the last reported level.
-    rc = enqueue_iter(0);
+    int rc = enqueue_iter(0);
     if (rc) return rc;
     rc = enqueue_iter(1);
     if (rc) return rc;
@@ -1154,8 +1158,12 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     for (;;) {
         rc = enqueue_iter(k + 1);
         if (rc) return rc;
-        CSBFS_HIP(hipEventSynchronize(e->count_ev[k & 1]));
-        const unsigned long long cnt = e->host_ctl[2 * (k & 1)];
+        unsigned long long cnt = 0;
+        rc = wait_count(mb, y, w, k, st, &cnt);
+        if (rc) {
+            (void)hipStreamSynchronize(st);
+            return rc;
+        }
         if (cnt == 0) break;
         if (++k > n) {  // every level visits a vertex: more than n levels is a broken count
             CSBFS_HIP(hipStreamSynchronize(st));
@@ -1164,12 +1172,11 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
     }
     const int64_t nl = k;  // levels 0..k-1
     *n_levels = (int32_t)(nl < INT32_MAX ? nl : INT32_MAX);
-    e->last_levels = *n_levels;
 
     // statistics
     int32_t hstatus = 0;
-    CSBFS_HIP(hipMemcpyAsync(&hstatus, e->status, sizeof(hstatus), hipMemcpyDeviceToHost, st));
-    const int64_t have = nl < e->L ? nl : e->L;
+    CSBFS_HIP(hipMemcpyAsync(&hstatus, w.status, sizeof(hstatus), hipMemcpyDeviceToHost, st));
+    const int64_t have = nl < y.L ? nl : y.L;
     const int64_t want = stats_cap < have ? stats_cap : have;
     std::vector<unsigned long long> ctl, ed, sb, uw, pl;
     std::vector<int64_t> wd;
@@ -1179,28 +1186,25 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         ed.resize(want);
         pl.resize(want);
         dr.resize(want);
-        CSBFS_HIP(hipMemcpyAsync(pl.data(), e->lc.pulled, sizeof(unsigned long long) * want,
-                                 hipMemcpyDeviceToHost, st));
-        CSBFS_HIP(hipMemcpyAsync(dr.data(), e->lc.dir, sizeof(int32_t) * want, hipMemcpyDeviceToHost, st));
         sb.resize(want * S);
         uw.resize(want * P);
         wd.resize(want * S);
-        CSBFS_HIP(hipMemcpyAsync(ctl.data(), e->lc.ctl, sizeof(unsigned long long) * 2 * want,
+        CSBFS_HIP(hipMemcpyAsync(pl.data(), w.lc.pulled, sizeof(unsigned long long) * want,
                                  hipMemcpyDeviceToHost, st));
-        CSBFS_HIP(hipMemcpyAsync(ed.data(), e->lc.edges, sizeof(unsigned long long) * want,
+        CSBFS_HIP(hipMemcpyAsync(dr.data(), w.lc.dir, sizeof(int32_t) * want, hipMemcpyDeviceToHost, st));
+        CSBFS_HIP(hipMemcpyAsync(ctl.data(), w.lc.ctl, sizeof(unsigned long long) * 2 * want,
                                  hipMemcpyDeviceToHost, st));
-        CSBFS_HIP(hipMemcpyAsync(sb.data(), e->lc.sbits, sizeof(unsigned long long) * want * S,
+        CSBFS_HIP(hipMemcpyAsync(ed.data(), w.lc.edges, sizeof(unsigned long long) * want,
                                  hipMemcpyDeviceToHost, st));
-        CSBFS_HIP(hipMemcpyAsync(uw.data(), e->lc.uwords, sizeof(unsigned long long) * want * P,
+        CSBFS_HIP(hipMemcpyAsync(sb.data(), w.lc.sbits, sizeof(unsigned long long) * want * S,
                                  hipMemcpyDeviceToHost, st));
-        CSBFS_HIP(hipMemcpyAsync(wd.data(), e->lc.words, sizeof(int64_t) * want * S,
+        CSBFS_HIP(hipMemcpyAsync(uw.data(), w.lc.uwords, sizeof(unsigned long long) * want * P,
+                                 hipMemcpyDeviceToHost, st));
+        CSBFS_HIP(hipMemcpyAsync(wd.data(), w.lc.words, sizeof(int64_t) * want * S,
                                  hipMemcpyDeviceToHost, st));
     }
     CSBFS_HIP(hipStreamSynchronize(st));
     if (hstatus != 0) {
-        // an encode that gave up waiting may have left look-back state behind
-        CSBFS_HIP(hipMemsetAsync(e->look, 0, e->look_bytes, st));
-        CSBFS_HIP(hipStreamSynchronize(st));
         if (hstatus == 1) return fail(CSBFS_ECORRUPT, "csbfs_bfs: a stream failed validation while decoding");
         return fail(CSBFS_ECORRUPT, "csbfs_bfs: internal consistency check failed");
     }
@@ -1246,51 +1250,247 @@ extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t 
         // the update of f^k runs inside its encoder: ms_update stays 0 and
         // ms_compress holds update + sieve + compress of level k
         for (int64_t lv = 0; lv < want; ++lv) {
-            hipEvent_t *ev = &e->events[(size_t)lv * kEvPerLevel];
-            float c = 0, d = 0, x = 0;
+            hipEvent_t *ev = &events[(size_t)lv * kEvPerLevel2];
+            float c = 0, d = 0, x = 0, b = 0;
             CSBFS_HIP(hipEventElapsedTime(&c, ev[0], ev[1]));
             CSBFS_HIP(hipEventElapsedTime(&d, ev[1], ev[2]));
             CSBFS_HIP(hipEventElapsedTime(&x, ev[2], ev[3]));
+            CSBFS_HIP(hipEventElapsedTime(&b, ev[3], ev[4]));
             stats[lv].ms_compress = c;
             stats[lv].ms_decode = d;
             stats[lv].ms_expand = x;
+            stats[lv].ms_long_rows = b;
             stats[lv].ms_update = 0.f;
         }
     }
     return CSBFS_OK;
 }
 
+int stream_words_of(const SearchLayout &y, const SearchState &w, int32_t last_levels, int32_t *words,
+                    int32_t cap_levels, hipStream_t st) {
+    const int64_t S = y.S;
+    const int64_t have = std::min<int64_t>(std::min<int64_t>(cap_levels, last_levels), y.L);
+    std::vector<int64_t> wd((size_t)(have > 0 ? have : 1) * S);
+    if (have > 0) {
+        CSBFS_HIP(hipMemcpyAsync(wd.data(), w.lc.words, sizeof(int64_t) * have * S, hipMemcpyDeviceToHost, st));
+        CSBFS_HIP(hipStreamSynchronize(st));
+    }
+    for (int64_t lv = 0; lv < cap_levels; ++lv)
+        for (int64_t s = 0; s < S; ++s) words[lv * S + s] = lv < have ? (int32_t)wd[lv * S + s] : 0;
+    return CSBFS_OK;
+}
+
+int copy_stream_of(const SearchLayout &y, const SearchState &w, int32_t last_levels, int32_t k, int32_t i,
+                   int32_t j, uint64_t *dst, int64_t cap_words, int64_t *n_words_out, hipStream_t st) {
+    if (!(y.flags & CSBFS_FLAG_KEEP_STREAMS))
+        return fail(CSBFS_EINVAL, "copy stream: the search did not keep its streams (CSBFS_FLAG_KEEP_STREAMS)");
+    if (k < 0 || k >= y.L || k >= last_levels || i < 0 || i >= y.P || j < 0 || j >= y.P)
+        return fail(CSBFS_EINVAL, "copy stream: level or processor out of range");
+    const int64_t s = (int64_t)i * y.P + j;
+    int64_t nw = 0;
+    CSBFS_HIP(hipMemcpyAsync(&nw, w.lc.words + (int64_t)k * y.S + s, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    *n_words_out = nw;
+    if (nw > cap_words) return fail(CSBFS_ENOSPACE, "copy stream: dst too small");
+    if (nw > 0)
+        CSBFS_HIP(hipMemcpyAsync(dst, w.arena + ((int64_t)k * y.S + s) * y.cap, sizeof(uint64_t) * nw,
+                                 hipMemcpyDeviceToDevice, st));
+    CSBFS_HIP(hipStreamSynchronize(st));
+    return CSBFS_OK;
+}
+
+int check_workspace(const csbfs_graph *g, const csbfs_search_config *cfg, void *ws, size_t ws_bytes,
+                    SearchLayout *y, const char *who) {
+    if (!g || !ws) return fail(CSBFS_EINVAL, std::string(who) + ": null graph or workspace");
+    int rc = search_layout(g->n, g->P, g->nnz, cfg, y);
+    if (rc) return rc;
+    if ((uintptr_t)ws % kAlign) return fail(CSBFS_EINVAL, std::string(who) + ": workspace must be 256-byte aligned");
+    if ((int64_t)ws_bytes < y->total)
+        return fail(CSBFS_ENOSPACE, std::string(who) + ": workspace smaller than csbfs_layout_query gives");
+    return CSBFS_OK;
+}
+
+}  // namespace
+}  // namespace csbfs
+
+using namespace csbfs;
+
+extern "C" int csbfs_layout_query(int64_t n, int64_t n_tuples, int32_t p, const csbfs_search_config *cfg,
+                                  csbfs_sizes *out) {
+    if (!out) return fail(CSBFS_EINVAL, "csbfs_layout_query: out is NULL");
+    GraphLayout gl;
+    int rc = graph_layout(n, n_tuples, p, &gl);
+    if (rc) return rc;
+    SearchLayout y;
+    rc = search_layout(n, p, 2 * n_tuples, cfg, &y);
+    if (rc) return rc;
+    out->graph_bytes = gl.graph_bytes;
+    out->build_scratch_bytes = gl.scratch_bytes;
+    out->workspace_bytes = y.total;
+    out->alignment = kAlign;
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_bfs_ws(const csbfs_graph *g, int64_t root, const csbfs_search_config *cfg, int32_t *level,
+                            int32_t *parent, csbfs_level_stats *stats, int32_t stats_cap, int32_t *n_levels,
+                            void *workspace, size_t ws_bytes, uint64_t *host_mailbox, void *stream) {
+    if (!g || !level || !parent || !n_levels || stats_cap < 0 || (stats_cap > 0 && !stats))
+        return fail(CSBFS_EINVAL, "csbfs_bfs_ws: null argument or negative stats_cap");
+    SearchLayout y;
+    int rc = check_workspace(g, cfg, workspace, ws_bytes, &y, "csbfs_bfs_ws");
+    if (rc) return rc;
+    if (root < 0 || root >= g->n) return fail(CSBFS_ERANGE, "csbfs_bfs_ws: root outside [0, n)");
+    rc = graph_device_check(g);
+    if (rc) return rc;
+    Mailbox mb;
+    if (host_mailbox) {
+        void *dev = nullptr;
+        const hipError_t e = hipHostGetDevicePointer(&dev, host_mailbox, 0);
+        if (e != hipSuccess || !dev) {
+            (void)hipGetLastError();  // the refusal must not surface at the next launch check
+            return fail(CSBFS_EINVAL, "csbfs_bfs_ws: host_mailbox is not pinned host memory");
+        }
+        mb.host = reinterpret_cast<volatile unsigned long long *>(host_mailbox);
+        mb.dev = (unsigned long long *)dev;
+    }
+    const SearchState w = bind_workspace(y, workspace);
+    return run_search(g, y, w, root, level, parent, stats, stats_cap, n_levels, mb, nullptr, as_stream(stream));
+}
+
+extern "C" int csbfs_ws_stream_words(const csbfs_graph *g, const csbfs_search_config *cfg, const void *workspace,
+                                     size_t ws_bytes, int32_t n_levels, int32_t *words, int32_t cap_levels,
+                                     void *stream) {
+    if (!words || cap_levels < 0 || n_levels < 0) return fail(CSBFS_EINVAL, "csbfs_ws_stream_words: bad argument");
+    SearchLayout y;
+    int rc = check_workspace(g, cfg, (void *)workspace, ws_bytes, &y, "csbfs_ws_stream_words");
+    if (rc) return rc;
+    return stream_words_of(y, bind_workspace(y, (void *)workspace), n_levels, words, cap_levels, as_stream(stream));
+}
+
+extern "C" int csbfs_ws_copy_stream(const csbfs_graph *g, const csbfs_search_config *cfg, const void *workspace,
+                                    size_t ws_bytes, int32_t n_levels, int32_t k, int32_t i, int32_t j,
+                                    uint64_t *dst, int64_t cap_words, int64_t *n_words_out, void *stream) {
+    if (!dst || !n_words_out) return fail(CSBFS_EINVAL, "csbfs_ws_copy_stream: null argument");
+    SearchLayout y;
+    int rc = check_workspace(g, cfg, (void *)workspace, ws_bytes, &y, "csbfs_ws_copy_stream");
+    if (rc) return rc;
+    return copy_stream_of(y, bind_workspace(y, (void *)workspace), n_levels, k, i, j, dst, cap_words, n_words_out,
+                          as_stream(stream));
+}
+
+// ------------------------------------------------------------------ engine --
+// A convenience owner of one workspace (device memory from hipMalloc), a
+// pinned mailbox and, with CSBFS_FLAG_TIMING, per-level events.
+
+struct csbfs_engine {
+    const csbfs_graph *g = nullptr;
+    csbfs_search_config cfg{};
+    SearchLayout y{};
+    void *ws = nullptr;
+    SearchState w{};
+    unsigned long long *mbox = nullptr;  // pinned [2]
+    Mailbox mb;
+    std::vector<hipEvent_t> events;
+    int32_t last_levels = 0;
+};
+
+namespace {
+
+void engine_release(csbfs_engine *e) {
+    if (e->ws) (void)hipFree(e->ws);
+    if (e->mbox) (void)hipHostFree(e->mbox);
+    for (hipEvent_t ev : e->events)
+        if (ev) (void)hipEventDestroy(ev);
+    delete e;
+}
+
+}  // namespace
+
+extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags,
+                                   csbfs_engine **out) {
+    if (!out) return fail(CSBFS_EINVAL, "csbfs_engine_create: out is NULL");
+    *out = nullptr;
+    if (!g) return fail(CSBFS_EINVAL, "csbfs_engine_create: graph is NULL");
+    if (max_levels < 1 || max_levels > 65536)
+        return fail(CSBFS_EINVAL, "csbfs_engine_create: max_levels outside [1, 65536]");
+    if (flags & ~(kSearchFlags | CSBFS_FLAG_TIMING)) return fail(CSBFS_EINVAL, "csbfs_engine_create: unknown flag");
+    int rc = graph_device_check(g);
+    if (rc) return rc;
+    std::unique_ptr<csbfs_engine> e(new csbfs_engine());
+    e->g = g;
+    e->cfg.flags = flags & kSearchFlags;
+    e->cfg.max_levels = max_levels;
+    rc = search_layout(g->n, g->P, g->nnz, &e->cfg, &e->y);
+    if (rc) return rc;
+    CSBFS_HIP(hipMalloc(&e->ws, (size_t)e->y.total));
+    e->w = bind_workspace(e->y, e->ws);
+    hipError_t herr = hipHostMalloc((void **)&e->mbox, 2 * sizeof(unsigned long long));
+    if (herr != hipSuccess) {
+        e->mbox = nullptr;
+        engine_release(e.release());
+        return hip_fail(herr, "hipHostMalloc", __FILE__, __LINE__);
+    }
+    void *dev = nullptr;
+    herr = hipHostGetDevicePointer(&dev, e->mbox, 0);
+    if (herr != hipSuccess) {
+        engine_release(e.release());
+        return hip_fail(herr, "hipHostGetDevicePointer", __FILE__, __LINE__);
+    }
+    e->mb.host = e->mbox;
+    e->mb.dev = (unsigned long long *)dev;
+    if (flags & CSBFS_FLAG_TIMING) {
+        e->events.assign((size_t)max_levels * kEvPerLevel2, nullptr);
+        for (auto &ev : e->events) {
+            herr = hipEventCreate(&ev);
+            if (herr != hipSuccess) {
+                ev = nullptr;
+                engine_release(e.release());
+                return hip_fail(herr, "hipEventCreate", __FILE__, __LINE__);
+            }
+        }
+    }
+    *out = e.release();
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_engine_set_direction(csbfs_engine *e, float alpha, float beta) {
+    if (!e) return fail(CSBFS_EINVAL, "csbfs_engine_set_direction: engine is NULL");
+    if (!(beta > 0.f) || alpha != alpha)
+        return fail(CSBFS_EINVAL, "csbfs_engine_set_direction: beta must be > 0 and alpha a number");
+    e->y.alpha = alpha;
+    e->y.beta = beta;
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_engine_free(csbfs_engine *e) {
+    if (!e) return CSBFS_OK;
+    engine_release(e);
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_bfs(csbfs_engine *e, int64_t root, int32_t *level, int32_t *parent,
+                         csbfs_level_stats *stats, int32_t stats_cap, int32_t *n_levels,
+                         void *stream) {
+    if (!e || !level || !parent || !n_levels || stats_cap < 0 || (stats_cap > 0 && !stats))
+        return fail(CSBFS_EINVAL, "csbfs_bfs: null argument or negative stats_cap");
+    const csbfs_graph *g = e->g;
+    if (root < 0 || root >= g->n) return fail(CSBFS_ERANGE, "csbfs_bfs: root outside [0, n)");
+    int rc = graph_device_check(g);
+    if (rc) return rc;
+    rc = run_search(g, e->y, e->w, root, level, parent, stats, stats_cap, n_levels, e->mb,
+                    e->events.empty() ? nullptr : e->events.data(), as_stream(stream));
+    e->last_levels = rc == CSBFS_OK ? *n_levels : 0;
+    return rc;
+}
+
 extern "C" int csbfs_engine_stream_words(const csbfs_engine *e, int32_t *words, int32_t cap_levels) {
     if (!e || !words || cap_levels < 0) return fail(CSBFS_EINVAL, "csbfs_engine_stream_words: bad argument");
-    const int64_t S = e->S;
-    std::vector<int64_t> wd((size_t)e->L * S);
-    CSBFS_HIP(hipMemcpy(wd.data(), e->lc.words, sizeof(int64_t) * e->L * S, hipMemcpyDeviceToHost));
-    for (int64_t lv = 0; lv < cap_levels; ++lv)
-        for (int64_t s = 0; s < S; ++s)
-            words[lv * S + s] = (lv < e->L && lv < e->last_levels) ? (int32_t)wd[lv * S + s] : 0;
-    return CSBFS_OK;
+    return stream_words_of(e->y, e->w, e->last_levels, words, cap_levels, nullptr);
 }
 
 extern "C" int csbfs_engine_copy_stream(const csbfs_engine *e, int32_t k, int32_t i, int32_t j,
                                         uint64_t *dst, int64_t cap_words, int64_t *n_words_out,
                                         void *stream) {
     if (!e || !dst || !n_words_out) return fail(CSBFS_EINVAL, "csbfs_engine_copy_stream: null argument");
-    if (!(e->flags & CSBFS_FLAG_KEEP_STREAMS))
-        return fail(CSBFS_EINVAL, "csbfs_engine_copy_stream: engine lacks CSBFS_FLAG_KEEP_STREAMS");
-    const int64_t P = e->g->P;
-    if (k < 0 || k >= e->L || k >= e->last_levels || i < 0 || i >= P || j < 0 || j >= P)
-        return fail(CSBFS_EINVAL, "csbfs_engine_copy_stream: level or processor out of range");
-    const int64_t s = (int64_t)i * P + j;
-    int64_t nw = 0;
-    hipStream_t st = as_stream(stream);
-    CSBFS_HIP(hipMemcpyAsync(&nw, e->lc.words + (int64_t)k * e->S + s, sizeof(int64_t),
-                             hipMemcpyDeviceToHost, st));
-    CSBFS_HIP(hipStreamSynchronize(st));
-    *n_words_out = nw;
-    if (nw > cap_words) return fail(CSBFS_ENOSPACE, "csbfs_engine_copy_stream: dst too small");
-    if (nw > 0)
-        CSBFS_HIP(hipMemcpyAsync(dst, e->arena + ((int64_t)k * e->S + s) * e->cap,
-                                 sizeof(uint64_t) * nw, hipMemcpyDeviceToDevice, st));
-    CSBFS_HIP(hipStreamSynchronize(st));
-    return CSBFS_OK;
+    return copy_stream_of(e->y, e->w, e->last_levels, k, i, j, dst, cap_words, n_words_out, as_stream(stream));
 }

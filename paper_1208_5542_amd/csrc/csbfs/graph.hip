@@ -228,6 +228,13 @@ __global__ void k_pull_fill(const int32_t *row_ptr, const int64_t *col_base, con
     }
 }
 
+// Vertices with at least one adjacency entry, one bit each.
+__global__ void k_live(const int32_t *deg, int64_t n, uint64_t *live) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const uint64_t b = __ballot(v < n && deg[v] > 0);
+    if ((threadIdx.x & 63) == 0 && v < n) live[v >> 6] = b;
+}
+
 unsigned grid_for(int64_t items, int64_t per_block, unsigned cap = 65536) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -235,19 +242,58 @@ unsigned grid_for(int64_t items, int64_t per_block, unsigned cap = 65536) {
     return (unsigned)g;
 }
 
-struct DevBuf {
-    void *p = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-    void *release() {
-        void *q = p;
-        p = nullptr;
-        return q;
-    }
-};
+constexpr int kMiscWords = 64;  // build flags and counters: err, sort queue counts, check, big items
+
+int check_sizes(int64_t n, int64_t n_tuples, int32_t p, const char *who) {
+    if (n_tuples < 0) return fail(CSBFS_EINVAL, std::string(who) + ": negative tuple count");
+    if (n < 64 || n >= ((int64_t)1 << 31)) return fail(CSBFS_ERANGE, std::string(who) + ": need 64 <= n < 2^31");
+    if (p < 1 || p > 64 || n % p != 0 || (n / p) % 64 != 0)
+        return fail(CSBFS_ERANGE, std::string(who) + ": need 1 <= p <= 64, p | n and 64 | n/p");
+    if (n_tuples > ((int64_t)1 << 40)) return fail(CSBFS_ERANGE, std::string(who) + ": too many tuples");
+    return CSBFS_OK;
+}
 
 }  // namespace
+
+int graph_layout(int64_t n, int64_t n_tuples, int32_t p, GraphLayout *L) {
+    const int rc = check_sizes(n, n_tuples, p, "graph layout");
+    if (rc) return rc;
+    GraphLayout g{};
+    g.n = n;
+    g.P = p;
+    g.R = n / p;
+    g.W = g.R / 64;
+    g.B = (int64_t)p * p;
+    g.nnz = 2 * n_tuples;
+    g.ntile = (g.R + kTile - 1) / kTile;
+    int64_t o = 0;
+    auto take = [&o](int64_t bytes) {
+        const int64_t at = o;
+        o += align_up(bytes > 0 ? bytes : 1);
+        return at;
+    };
+    g.row_ptr = take(4 * g.B * (g.R + 1));
+    g.col_base = take(8 * (g.B + 1));
+    g.col = take(4 * g.nnz);
+    g.dir = take(8 * g.B * g.W);
+    g.deg = take(4 * n);
+    g.pull_off = take(8 * (n + 1));
+    g.pull_col = take(4 * g.nnz);
+    g.live = take(8 * (n / 64));
+    g.qoff = take(8 * (g.P + 1));
+    g.small = take(8 * 64);
+    g.graph_bytes = o;
+    o = 0;
+    g.cnt = take(4 * g.B * g.R);
+    g.sums = take(8 * g.B * g.ntile);
+    g.nnzb = take(8 * g.B);
+    g.misc = take(8 * (kMiscWords + g.P));
+    g.queues = take(8 * (sort_queue_cap(g.nnz, 0) + sort_queue_cap(g.nnz, 1) + sort_queue_cap(g.nnz, 2)));
+    g.scan = take(8 * scan_tiles(n));
+    g.scratch_bytes = o;
+    *L = g;
+    return CSBFS_OK;
+}
 
 int graph_device_check(const csbfs_graph *g) {
     int dev = -1;
@@ -260,20 +306,25 @@ int graph_device_check(const csbfs_graph *g) {
 
 using namespace csbfs;
 
-extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t n_tuples,
-                                 int64_t n, int32_t p, void *stream, csbfs_graph **out) {
-    if (!out) return fail(CSBFS_EINVAL, "csbfs_graph_build: out is NULL");
+extern "C" int csbfs_graph_build_into(const int64_t *src, const int64_t *dst, int64_t n_tuples, int64_t n,
+                                      int32_t p, void *graph_mem, size_t graph_bytes, void *scratch,
+                                      size_t scratch_bytes, void *stream, csbfs_graph **out) {
+    if (!out) return fail(CSBFS_EINVAL, "csbfs_graph_build_into: out is NULL");
     *out = nullptr;
     if (n_tuples < 0 || (n_tuples > 0 && (!src || !dst)))
-        return fail(CSBFS_EINVAL, "csbfs_graph_build: null tuple arrays or negative count");
-    if (n < 64 || n >= ((int64_t)1 << 31))
-        return fail(CSBFS_ERANGE, "csbfs_graph_build: need 64 <= n < 2^31");
-    if (p < 1 || p > 64 || n % p != 0 || (n / p) % 64 != 0)
-        return fail(CSBFS_ERANGE, "csbfs_graph_build: need 1 <= p <= 64, p | n and 64 | n/p");
-    if (n_tuples > ((int64_t)1 << 40))
-        return fail(CSBFS_ERANGE, "csbfs_graph_build: too many tuples");
+        return fail(CSBFS_EINVAL, "csbfs_graph_build_into: null tuple arrays or negative count");
+    GraphLayout L;
+    int rc = graph_layout(n, n_tuples, p, &L);
+    if (rc) return rc;
+    if (!graph_mem || !scratch) return fail(CSBFS_EINVAL, "csbfs_graph_build_into: null graph or scratch buffer");
+    if ((uintptr_t)graph_mem % kAlign || (uintptr_t)scratch % kAlign)
+        return fail(CSBFS_EINVAL, "csbfs_graph_build_into: buffers must be 256-byte aligned");
+    if ((int64_t)graph_bytes < L.graph_bytes || (int64_t)scratch_bytes < L.scratch_bytes)
+        return fail(CSBFS_ENOSPACE, "csbfs_graph_build_into: graph or scratch buffer smaller than "
+                                    "csbfs_layout_query gives");
     hipStream_t st = as_stream(stream);
-    const int64_t R = n / p, W = R / 64, B = (int64_t)p * p;
+    const int64_t R = L.R, W = L.W, B = L.B, ntile = L.ntile;
+    char *gm = (char *)graph_mem, *sm = (char *)scratch;
 
     std::unique_ptr<csbfs_graph> g(new csbfs_graph());
     CSBFS_HIP(hipGetDevice(&g->device));
@@ -282,139 +333,150 @@ extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t
     g->R = R;
     g->W = W;
     g->n_tuples = n_tuples;
+    g->row_ptr = (int32_t *)(gm + L.row_ptr);
+    g->col_base = (int64_t *)(gm + L.col_base);
+    g->col = (uint32_t *)(gm + L.col);
+    g->dir = (uint64_t *)(gm + L.dir);
+    g->deg = (int32_t *)(gm + L.deg);
+    g->pull_off = (int64_t *)(gm + L.pull_off);
+    g->pull_col = (uint32_t *)(gm + L.pull_col);
+    g->live = (uint64_t *)(gm + L.live);
+    g->qoff = (int64_t *)(gm + L.qoff);
+    g->scratch = (unsigned long long *)(gm + L.small);
+    int32_t *cnt = (int32_t *)(sm + L.cnt);
+    long long *sums = (long long *)(sm + L.sums);
+    long long *nnzb = (long long *)(sm + L.nnzb);
+    unsigned long long *misc = (unsigned long long *)(sm + L.misc);
+    int32_t *err = (int32_t *)misc;
+    unsigned long long *qcount = misc + 8, *chk = misc + 16, *big = misc + kMiscWords;
 
-    DevBuf cnt, sums, nnzb, err, rp, cb, col, dir, deg, scratch, poff, pcol;
-    const int64_t ntile = (R + kTile - 1) / kTile;
-    CSBFS_HIP(hipMalloc(&cnt.p, sizeof(int32_t) * B * R));
-    CSBFS_HIP(hipMalloc(&sums.p, sizeof(long long) * B * ntile));
-    CSBFS_HIP(hipMalloc(&nnzb.p, sizeof(long long) * B));
-    CSBFS_HIP(hipMalloc(&err.p, sizeof(int32_t)));
-    CSBFS_HIP(hipMalloc(&rp.p, sizeof(int32_t) * B * (R + 1)));
-    CSBFS_HIP(hipMalloc(&cb.p, sizeof(int64_t) * (B + 1)));
-    CSBFS_HIP(hipMalloc(&dir.p, sizeof(uint64_t) * B * W));
-    CSBFS_HIP(hipMalloc(&deg.p, sizeof(int32_t) * n));
-    CSBFS_HIP(hipMalloc(&scratch.p, 8 * 64));
-    CSBFS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * B * R, st));
-    CSBFS_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
-
+    CSBFS_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * B * R, st));
+    CSBFS_HIP(hipMemsetAsync(misc, 0, sizeof(unsigned long long) * (kMiscWords + p), st));
     if (n_tuples > 0) {
         hipLaunchKernelGGL(k_count, dim3(grid_for(n_tuples, kThreads)), dim3(kThreads), 0, st, src,
-                           dst, n_tuples, n, R, p, (int32_t *)cnt.p, (int32_t *)err.p);
+                           dst, n_tuples, n, R, p, cnt, err);
         CSBFS_HIP(hipGetLastError());
     }
     int32_t herr = 0;
-    CSBFS_HIP(hipMemcpyAsync(&herr, err.p, sizeof(herr), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, st));
     CSBFS_HIP(hipStreamSynchronize(st));
-    if (herr) return fail(CSBFS_ERANGE, "csbfs_graph_build: a tuple id is outside [0, n)");
+    if (herr) return fail(CSBFS_ERANGE, "csbfs_graph_build_into: a tuple id is outside [0, n)");
 
     hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)ntile, (unsigned)B), dim3(kThreads), 0, st,
-                       (const int32_t *)cnt.p, R, ntile, (long long *)sums.p);
+                       (const int32_t *)cnt, R, ntile, sums);
     CSBFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)B), dim3(kThreads), 0, st, (long long *)sums.p,
-                       ntile, (long long *)nnzb.p);
+    hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)B), dim3(kThreads), 0, st, sums, ntile, nnzb);
     CSBFS_HIP(hipGetLastError());
     std::vector<long long> nnz(B);
-    CSBFS_HIP(hipMemcpyAsync(nnz.data(), nnzb.p, sizeof(long long) * B, hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipMemcpyAsync(nnz.data(), nnzb, sizeof(long long) * B, hipMemcpyDeviceToHost, st));
     CSBFS_HIP(hipStreamSynchronize(st));
     std::vector<int64_t> base(B + 1, 0);
     int64_t maxb = 0;
     for (int64_t b = 0; b < B; ++b) {
         if (nnz[b] >= ((long long)1 << 31) - 1)
-            return fail(CSBFS_EOVERFLOW, "csbfs_graph_build: a sub-block has >= 2^31 entries");
+            return fail(CSBFS_EOVERFLOW, "csbfs_graph_build_into: a sub-block has >= 2^31 entries");
         base[b + 1] = base[b] + nnz[b];
         if (nnz[b] > maxb) maxb = nnz[b];
     }
     const int64_t total = base[B];
-    CSBFS_HIP(hipMemcpyAsync(cb.p, base.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_tile_apply, dim3((unsigned)ntile, (unsigned)B), dim3(kThreads), 0, st,
-                       (int32_t *)cnt.p, R, ntile, (const long long *)sums.p, (int32_t *)rp.p);
+    if (total != L.nnz) return fail(CSBFS_ECORRUPT, "csbfs_graph_build_into: adjacency count mismatch");
+    CSBFS_HIP(hipMemcpyAsync(g->col_base, base.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_tile_apply, dim3((unsigned)ntile, (unsigned)B), dim3(kThreads), 0, st, cnt, R,
+                       ntile, (const long long *)sums, g->row_ptr);
     CSBFS_HIP(hipGetLastError());
-    CSBFS_HIP(hipMalloc(&col.p, sizeof(uint32_t) * (total > 0 ? total : 1)));
     if (n_tuples > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_tuples, kThreads)), dim3(kThreads), 0, st,
-                           src, dst, n_tuples, R, p, (int32_t *)cnt.p, (const int64_t *)cb.p,
-                           (uint32_t *)col.p);
+                           src, dst, n_tuples, R, p, cnt, (const int64_t *)g->col_base, g->col);
         CSBFS_HIP(hipGetLastError());
     }
-    {
-        uint32_t *c = (uint32_t *)col.p;
-        int src_rc = sort_rows_desc(&c, base.data(), (const int32_t *)rp.p, R, p, total, st);
-        col.p = c;
-        if (src_rc) return src_rc;
-    }
+    // rows in decreasing id order; pull_col serves as the sort's temp buffer
+    // (it is filled from the sorted blocks afterwards)
+    rc = sort_rows_desc(g->col, g->pull_col, g->row_ptr, g->col_base, R, p, total,
+                        (int64_t *)(sm + L.queues), qcount, err, st);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_directory, dim3(grid_for(B * W * 64, kThreads)), dim3(kThreads), 0, st,
-                       (const int32_t *)rp.p, R, W, B, (uint64_t *)dir.p);
+                       (const int32_t *)g->row_ptr, R, W, B, g->dir);
     CSBFS_HIP(hipGetLastError());
-    CSBFS_HIP(hipMemsetAsync(scratch.p, 0, 8 * 64, st));
     hipLaunchKernelGGL(k_degree, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st,
-                       (const int32_t *)rp.p, R, p, n, (int32_t *)deg.p,
-                       (unsigned long long *)scratch.p);
+                       (const int32_t *)g->row_ptr, R, p, n, g->deg, big);
     CSBFS_HIP(hipGetLastError());
-    std::vector<unsigned long long> big_items(p);
-    CSBFS_HIP(hipMemcpyAsync(big_items.data(), scratch.p, sizeof(unsigned long long) * p,
-                             hipMemcpyDeviceToHost, st));
-    CSBFS_HIP(hipStreamSynchronize(st));
+    hipLaunchKernelGGL(k_live, dim3(grid_for(n, 256, 1u << 30)), dim3(256), 0, st, (const int32_t *)g->deg, n,
+                       g->live);
+    CSBFS_HIP(hipGetLastError());
     // never hand the search a column id outside its block or a lost entry
-    CSBFS_HIP(hipMemsetAsync(scratch.p, 0, 2 * sizeof(unsigned long long), st));
-    hipLaunchKernelGGL(k_check, dim3(4096), dim3(kThreads), 0, st, (const uint32_t *)col.p, total,
-                       (const int32_t *)deg.p, n, (unsigned long long *)scratch.p);
+    hipLaunchKernelGGL(k_check, dim3(4096), dim3(kThreads), 0, st, (const uint32_t *)g->col, total,
+                       (const int32_t *)g->deg, n, chk);
     CSBFS_HIP(hipGetLastError());
-    unsigned long long chk[2] = {0, 0};
-    CSBFS_HIP(hipMemcpyAsync(chk, scratch.p, sizeof(chk), hipMemcpyDeviceToHost, st));
-    CSBFS_HIP(hipStreamSynchronize(st));
-    if (total > 0 && (chk[0] >= (unsigned long long)R || chk[1] != (unsigned long long)total))
-        return fail(CSBFS_ECORRUPT, "csbfs_graph_build: internal consistency check of the block "
-                                    "CSR failed (column id or degree total)");
-    // pull layout for the bottom-up evaluation
-    CSBFS_HIP(cnt.p ? hipFree(cnt.release()) : hipSuccess);
-    CSBFS_HIP(hipMalloc(&poff.p, sizeof(int64_t) * (n + 1)));
-    CSBFS_HIP(hipMalloc(&pcol.p, sizeof(uint32_t) * (total > 0 ? total : 1)));
-    {
-        const int rc = degree_offsets((const int32_t *)deg.p, n, (int64_t *)poff.p, st);
-        if (rc) return rc;
-    }
+    rc = degree_offsets(g->deg, n, g->pull_off, (int64_t *)(sm + L.scan), st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_pull_fill, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st,
+                       (const int32_t *)g->row_ptr, (const int64_t *)g->col_base, (const uint32_t *)g->col, R, p,
+                       n, (const int64_t *)g->pull_off, g->pull_col);
+    CSBFS_HIP(hipGetLastError());
+    std::vector<unsigned long long> tail(kMiscWords + p);
     int64_t pull_total = -1;
-    CSBFS_HIP(hipMemcpyAsync(&pull_total, (const int64_t *)poff.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipMemcpyAsync(tail.data(), misc, sizeof(unsigned long long) * (kMiscWords + p),
+                             hipMemcpyDeviceToHost, st));
+    CSBFS_HIP(hipMemcpyAsync(&pull_total, g->pull_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     CSBFS_HIP(hipStreamSynchronize(st));
+    if ((int32_t)tail[0] != 0)
+        return fail(CSBFS_ECORRUPT, "csbfs_graph_build_into: internal row-sort queue overflow");
+    if (total > 0 && (tail[16] >= (unsigned long long)R || tail[17] != (unsigned long long)total))
+        return fail(CSBFS_ECORRUPT, "csbfs_graph_build_into: internal consistency check of the block "
+                                    "CSR failed (column id or degree total)");
     if (pull_total != total)
-        return fail(CSBFS_ECORRUPT, "csbfs_graph_build: pull-row offsets disagree with the blocks");
-    hipLaunchKernelGGL(k_pull_fill, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st, (const int32_t *)rp.p,
-                       (const int64_t *)cb.p, (const uint32_t *)col.p, R, p, n, (const int64_t *)poff.p,
-                       (uint32_t *)pcol.p);
-    CSBFS_HIP(hipGetLastError());
+        return fail(CSBFS_ECORRUPT, "csbfs_graph_build_into: pull-row offsets disagree with the blocks");
+    // chunk-queue regions per processor, from the long rows each block-row has
+    std::vector<int64_t> qoff(p + 1, 0);
+    g->big_items.assign(p, 0);
+    for (int32_t r = 0; r < p; ++r) {
+        g->big_items[r] = (int64_t)tail[kMiscWords + r];
+        qoff[r + 1] = qoff[r] + g->big_items[r];
+    }
+    if (qoff[p] > big_items_bound(total))
+        return fail(CSBFS_ECORRUPT, "csbfs_graph_build_into: chunk-queue items above their bound");
+    CSBFS_HIP(hipMemcpyAsync(g->qoff, qoff.data(), sizeof(int64_t) * (p + 1), hipMemcpyHostToDevice, st));
     CSBFS_HIP(hipStreamSynchronize(st));
-
-    g->row_ptr = (int32_t *)rp.release();
-    g->col_base = (int64_t *)cb.release();
     g->col_base_host = base;
-    g->col = (uint32_t *)col.release();
-    g->dir = (uint64_t *)dir.release();
-    g->deg = (int32_t *)deg.release();
-    g->pull_off = (int64_t *)poff.release();
-    g->pull_col = (uint32_t *)pcol.release();
-    g->scratch = (unsigned long long *)scratch.release();
     g->nnz = total;
     g->max_block_nnz = maxb;
-    g->big_items.assign(big_items.begin(), big_items.end());
-    g->device_bytes = (int64_t)(sizeof(int32_t) * B * (R + 1) + sizeof(int64_t) * (B + 1) +
-                                sizeof(uint32_t) * total + sizeof(uint64_t) * B * W +
-                                sizeof(int32_t) * n + 8 * 64 + sizeof(int64_t) * (n + 1) +
-                                sizeof(uint32_t) * total);
+    g->device_bytes = L.graph_bytes;
     *out = g.release();
+    return CSBFS_OK;
+}
+
+extern "C" int csbfs_graph_build(const int64_t *src, const int64_t *dst, int64_t n_tuples,
+                                 int64_t n, int32_t p, void *stream, csbfs_graph **out) {
+    if (!out) return fail(CSBFS_EINVAL, "csbfs_graph_build: out is NULL");
+    *out = nullptr;
+    if (n_tuples < 0 || (n_tuples > 0 && (!src || !dst)))
+        return fail(CSBFS_EINVAL, "csbfs_graph_build: null tuple arrays or negative count");
+    GraphLayout L;
+    int rc = graph_layout(n, n_tuples, p, &L);
+    if (rc) return rc;
+    void *gm = nullptr, *sm = nullptr;
+    CSBFS_HIP(hipMalloc(&gm, (size_t)L.graph_bytes));
+    hipError_t e = hipMalloc(&sm, (size_t)L.scratch_bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(gm);
+        return hip_fail(e, "hipMalloc(build scratch)", __FILE__, __LINE__);
+    }
+    rc = csbfs_graph_build_into(src, dst, n_tuples, n, p, gm, (size_t)L.graph_bytes, sm,
+                                (size_t)L.scratch_bytes, stream, out);
+    (void)hipFree(sm);
+    if (rc) {
+        (void)hipFree(gm);
+        return rc;
+    }
+    (*out)->owned = gm;
     return CSBFS_OK;
 }
 
 extern "C" int csbfs_graph_free(csbfs_graph *g) {
     if (!g) return CSBFS_OK;
-    (void)hipDeviceSynchronize();
-    (void)hipFree(g->row_ptr);
-    (void)hipFree(g->col_base);
-    (void)hipFree(g->col);
-    (void)hipFree(g->dir);
-    (void)hipFree(g->deg);
-    (void)hipFree(g->pull_off);
-    (void)hipFree(g->pull_col);
-    (void)hipFree(g->scratch);
+    // a caller-owned buffer stays the caller's; hipFree orders itself after
+    // the device work that may still use the library's own buffer
+    if (g->owned) (void)hipFree(g->owned);
     delete g;
     return CSBFS_OK;
 }

@@ -170,7 +170,7 @@ __device__ __forceinline__ void stage(const WahBatch &b, int64_t s, const SegGeo
         uint64_t v = h.load(b, x.r, i, w);
         if (tail && w == b.words_per_piece - 1) v &= (1ull << tail) - 1;
         if (su) su[k] = v;
-        if (mask) v &= mask[w];
+        if (mask && v) v &= mask[w];  // a zero word needs no directory word
         sw[k] = v;
     }
     __syncthreads();
@@ -524,8 +524,8 @@ __device__ __forceinline__ void dec_count_body(const WahBatch &b) {
     if (threadIdx.x == 0) b.chunk_groups[s * b.nchunk + c] = groups;
 }
 
-__device__ __forceinline__ void dec_scatter_body(const WahBatch &b) {
-    const int64_t c = blockIdx.x;
+__device__ __forceinline__ void dec_scatter_body(const WahBatch &b, int64_t c = -1) {
+    if (c < 0) c = blockIdx.x;
     const int64_t s = blockIdx.y;
     if (plane_skipped(b, s)) return;
     const StreamIdx si = stream_idx(s, b.P);

@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_version_and_status_strings(lib):
     from paper_1208_5542_amd import csbfs
-    assert csbfs.version() == 10100
+    assert csbfs.version() == 10200
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert csbfs.strerror(code) != "unknown status"
     assert csbfs.strerror(-99) == "unknown status"
@@ -128,3 +128,44 @@ def test_level_stats_layout_matches_header():
     names = re.findall(r"\b(?:int64_t|int32_t|float)\s+(\w+);", body)
     assert names == [f[0] for f in csbfs.LevelStats._fields_]
     assert ctypes.sizeof(csbfs.LevelStats) == 11 * 8 + 4 * 4 + 2 * 4
+
+
+def test_layout_query_is_host_only_and_exact_in_its_inputs():
+    """csbfs_layout_query needs no device, depends only on its arguments and
+    grows with the config's kept levels and streams."""
+    from paper_1208_5542_amd import csbfs
+    a = csbfs.layout_query(1 << 22, 1 << 26, 4)
+    assert a == csbfs.layout_query(1 << 22, 1 << 26, 4)
+    assert a["alignment"] == 256
+    for k in ("graph_bytes", "build_scratch_bytes", "workspace_bytes"):
+        assert a[k] > 0 and a[k] % 256 == 0
+    # the graph holds the column ids twice (blocks and merged pull rows)
+    assert a["graph_bytes"] >= 2 * 4 * 2 * (1 << 26)
+    keep = csbfs.layout_query(1 << 22, 1 << 26, 4, csbfs.search_config(flags=csbfs.FLAG_KEEP_STREAMS,
+                                                                      max_levels=64))
+    assert keep["graph_bytes"] == a["graph_bytes"] and keep["workspace_bytes"] > a["workspace_bytes"]
+    deeper = csbfs.layout_query(1 << 22, 1 << 26, 4, csbfs.search_config(max_levels=1000))
+    assert deeper["workspace_bytes"] > a["workspace_bytes"]
+    with pytest.raises(csbfs.CsbfsError) as ei:
+        csbfs.layout_query(1000, 10, 4)
+    assert ei.value.status == csbfs.ERANGE
+    with pytest.raises(csbfs.CsbfsError) as ei:
+        csbfs.layout_query(1 << 12, -1, 4)
+    assert ei.value.status == csbfs.EINVAL
+    for bad in (csbfs.search_config(flags=csbfs.FLAG_TIMING), csbfs.search_config(flags=8 | 16),
+                csbfs.search_config(max_levels=70000), csbfs.search_config(segment_groups=512),
+                csbfs.SearchConfig(0, 64, 0.0, 0.0, 0, 1)):
+        with pytest.raises(csbfs.CsbfsError) as ei:
+            csbfs.layout_query(1 << 12, 100, 4, bad)
+        assert ei.value.status == csbfs.EINVAL
+
+
+def test_search_config_layout_matches_header():
+    from paper_1208_5542_amd import csbfs
+    assert _struct_fields("csbfs_sizes") == [f[0] for f in csbfs.Sizes._fields_]
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct csbfs_search_config {"):text.index("} csbfs_search_config;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b(?:uint32_t|int32_t|float)\s+(\w+);", body)
+    assert names == [f[0] for f in csbfs.SearchConfig._fields_]
+    assert ctypes.sizeof(csbfs.SearchConfig) == 24 and ctypes.sizeof(csbfs.Sizes) == 32

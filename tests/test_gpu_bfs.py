@@ -96,6 +96,33 @@ def _check_search(eng, g, n, p, src, dst, root, adj, V, keep=True, max_levels=64
     return r
 
 
+def test_volume_p3_example(golden):
+    """The hand-derived p = 3 example of Sec. VI.A's volume: stream lengths
+    per level, per-level maximum of a processor's sent plus received bytes,
+    and (from the word counts) every processor's volume over the search."""
+    from paper_1208_5542_amd import csbfs
+    gd = golden("volume_p3_example.json")
+    n, p = gd["n"], gd["p"]
+    g = csbfs.Graph(_dev(gd["src"]), _dev(gd["dst"]), n, p)
+    for flags in (0, csbfs.FLAG_SPARSE_ONLY, csbfs.FLAG_BOTTOM_UP_ONLY):
+        eng = csbfs.Engine(g, flags=flags)
+        r = eng.bfs(gd["root"])
+        lev = r.level.cpu().numpy()
+        assert r.n_levels == gd["n_levels"]
+        for k, vs in gd["levels"].items():
+            assert sorted(np.flatnonzero(lev == int(k)).tolist()) == vs
+        words = eng.stream_words(r.n_levels)
+        assert words.tolist() == gd["words"]
+        assert [s["wah_sieved_bytes"] for s in r.stats] == gd["wah_sieved_bytes"]
+        assert [s["self_bytes"] for s in r.stats] == gd["self_bytes"]
+        assert [s["max_rank_bytes"] for s in r.stats] == gd["per_level_max_rank_bytes"]
+        sent = [8 * int(sum(words[k, i, j] for k in range(r.n_levels) for j in range(p) if j != i))
+                for i in range(p)]
+        recv = [8 * int(sum(words[k, i, j] for k in range(r.n_levels) for i in range(p) if j != i))
+                for j in range(p)]
+        assert sent == gd["rank_sent_bytes"] and recv == gd["rank_received_bytes"]
+
+
 MODES = {"auto": 0, "sparse": 8, "dense": 16, "bottom_up": 32}
 
 
@@ -115,21 +142,22 @@ def test_search_matches_oracle(scale, p, nroots, mode):
         _check_search(eng, g, n, p, src, dst, int(root), adj, V)
 
 
-@pytest.mark.parametrize("gpt", ["2", "4"])
-def test_encoder_segment_sizes(gpt, monkeypatch):
+@pytest.mark.parametrize("groups", [1024, 2048])
+def test_encoder_segment_sizes(groups):
     """Both segment sizes of the search's encoder (1024 and 2048 groups), on
     pieces of several segments: R-MAT scale 20 on a 4 x 4 grid (2^18 bits per
-    piece), streams byte-identical to the oracle's Algorithm 3."""
+    piece), streams byte-identical to the oracle's Algorithm 3; searched in a
+    caller workspace whose config fixes the segment size."""
     from paper_1208_5542_amd import csbfs
-    monkeypatch.setenv("CSBFS_ENC_GPT", gpt)
     scale, p = 20, 4
     n, src, dst = _graph(scale)
     g = csbfs.Graph(_dev(src), _dev(dst), n, p)
-    eng = csbfs.Engine(g, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS)
+    eng = csbfs.WorkspaceSearch(g, csbfs.search_config(flags=csbfs.FLAG_KEEP_STREAMS, max_levels=64,
+                                                       segment_groups=groups))
     adj = oracle.Adjacency(n, src, dst)
     V = oracle.directory(n, p, src, dst).reshape(-1)
     for root in inputs.pick_roots(n, src, dst, 2, inputs.graph_seed(scale) + 2):
-        log(f"search scale={scale} p={p} segment groups={512 * int(gpt)} root={int(root)}")
+        log(f"search scale={scale} p={p} segment groups={groups} root={int(root)}")
         _check_search(eng, g, n, p, src, dst, int(root), adj, V)
 
 
@@ -266,7 +294,9 @@ def test_no_sieve_flag_gives_same_search():
     ref = adj.alg3(p, ones, root)
     assert (b.stream_words(rb.n_levels) == ref.words).all()
     for k in range(1, ra.n_levels):
-        assert ra.stats[k]["wah_sieved_bytes"] <= rb.stats[k]["wah_sieved_bytes"]
+        # the sieve only drops bits (WAH bytes need not shrink)
+        assert ra.stats[k]["sieved_bits"] <= rb.stats[k]["sieved_bits"]
+        assert rb.stats[k]["sieved_bits"] == rb.stats[k]["unsieved_bits"]
         assert rb.stats[k]["wah_sieved_bytes"] == rb.stats[k]["wah_unsieved_bytes"]
 
 
