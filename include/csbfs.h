@@ -545,6 +545,25 @@ int csbfs_wah_encode(const uint64_t *bits, const uint64_t *mask, int64_t nbits, 
                      void *stream);
 
 /*
+ * Sieve and compress with no workspace argument and no allocation of any
+ * kind, for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. Same arguments,
+ * stream and errors as csbfs_wah_encode without the workspace. The
+ * encoder's look-back words and tickets live in a fixed 256 KiB device array
+ * inside the library (one per GPU, held until the process ends), which
+ * bounds nbits by csbfs_wah_noalloc_max_bits() (above 4 * 10^9 bits): a
+ * larger nbits fails with EINVAL. The array is cleared by a kernel at every
+ * call (no memset node). Every call on one GPU shares that array: calls
+ * that overlap in time on one GPU (concurrent streams or threads) race and
+ * must be serialized by the caller. Asynchronous.
+ */
+int csbfs_wah_encode_noalloc(const uint64_t *bits, const uint64_t *mask, int64_t nbits, uint64_t *out,
+                             int64_t cap_words, int64_t *n_words, void *stream);
+
+/* Largest nbits csbfs_wah_encode_noalloc accepts (host arithmetic only). */
+int64_t csbfs_wah_noalloc_max_bits(void);
+
+/*
  * Uncompress: OR the nbits bits of a WAH-64 stream of n_words words into dst
  * (device uint64[ceil(nbits/64)]; zero it first for a plain decode).
  *   status  device int32[1]: set to 0 if the stream is a valid encoding of

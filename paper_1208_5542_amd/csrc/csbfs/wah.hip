@@ -1,6 +1,8 @@
 // WAH-64 sieve + compress and decompress kernels (Sec. IV, Table 3; Alg. 3
 // sieve, Compress and Uncompress), batched over the p * p streams of a level;
 // the device code is in wah_device.hpp.
+#include <mutex>
+
 #include "wah_device.hpp"
 
 namespace csbfs {
@@ -14,6 +16,16 @@ __global__ __launch_bounds__(kEncThreads) void wah_encode_kernel(WahBatch b) {
 __global__ __launch_bounds__(kDecThreads) void wah_dec_count(WahBatch b) { dec_count_body(b); }
 
 __global__ __launch_bounds__(kDecThreads) void wah_dec_scatter(WahBatch b) { dec_scatter_body(b); }
+
+// Zero `words` 32-bit words (a kernel rather than a memset node, so that the
+// allocation-free entry point can be captured into a HIP graph).
+__global__ void zero_words_kernel(uint32_t *p, int64_t words) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < words;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = 0;
+}
+
+__global__ void store_i64_kernel(int64_t *p, int64_t v) { *p = v; }
 
 }  // namespace
 
@@ -101,6 +113,93 @@ extern "C" int csbfs_wah_encode(const uint64_t *bits, const uint64_t *mask, int6
     // may hold anything)
     CSBFS_HIP(hipMemsetAsync(ws + l.look, 0, l.chunk_groups - l.look, as_stream(stream)));
     return launch_wah_encode(b, as_stream(stream));
+}
+
+// ------------------------------------------- allocation-free encoder ---
+//
+// Scratch of csbfs_wah_encode_noalloc: the encoder's look-back words and
+// segment tickets, in a file-scope device array. Each GPU the library runs
+// on holds its own copy until the process ends. Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in symbol): the
+// device address is looked up once per device with hipGetSymbolAddress and
+// that pointer is used everywhere.
+namespace {
+constexpr size_t kNoAllocScratchBytes = 256 * 1024;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_ptr(void **out) {
+    int dev = -1;
+    CSBFS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CSBFS_EINVAL, "csbfs_wah_encode_noalloc: device id out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CSBFS_OK;
+}
+}  // namespace
+
+extern "C" int64_t csbfs_wah_noalloc_max_bits(void) {
+    // the largest nbits whose look-back words and tickets fit the scratch
+    int64_t lo = 0, hi = 63 * (int64_t)kLbField;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        const WsLayout l = ws_layout(mid);
+        if (l.chunk_groups <= kNoAllocScratchBytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+extern "C" int csbfs_wah_encode_noalloc(const uint64_t *bits, const uint64_t *mask, int64_t nbits, uint64_t *out,
+                                        int64_t cap_words, int64_t *n_words, void *stream) {
+    if (nbits < 0 || !out || !n_words || (nbits > 0 && !bits))
+        return fail(CSBFS_EINVAL, "csbfs_wah_encode_noalloc: null pointer or negative size");
+    if (nbits > csbfs_wah_noalloc_max_bits())
+        return fail(CSBFS_EINVAL, "csbfs_wah_encode_noalloc: nbits above csbfs_wah_noalloc_max_bits() (the "
+                                  "encoder's scratch is a fixed 256 KiB device array)");
+    if (cap_words < wah_cap(nbits))
+        return fail(CSBFS_ENOSPACE, "csbfs_wah_encode_noalloc: output capacity below floor(nbits/63)+1");
+    void *ptr = nullptr;
+    int rc = scratch_ptr(&ptr);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    if (nbits == 0) {
+        hipLaunchKernelGGL(store_i64_kernel, dim3(1), dim3(1), 0, st, n_words, (int64_t)0);
+        CSBFS_HIP(hipGetLastError());
+        return CSBFS_OK;
+    }
+    const WsLayout l = ws_layout(nbits);
+    char *ws = (char *)ptr;
+    // look-back words and tickets start at zero; the previous call on this
+    // device left them zero unless it failed, so clear them every time
+    const int64_t words = (int64_t)((l.chunk_groups - l.look) / 4);
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st,
+                       (uint32_t *)(ws + l.look), words);
+    CSBFS_HIP(hipGetLastError());
+    WahBatch b{};
+    b.bits_base = bits;
+    b.mask_base = mask;
+    b.out_base = out;
+    b.n_words = n_words;
+    b.nbits = nbits;
+    b.words_per_piece = (nbits + 63) / 64;
+    b.cap = cap_words;
+    b.P = 1;
+    b.look = (unsigned long long *)(ws + l.look);
+    b.ticket = (uint32_t *)(ws + l.ticket);
+    b.nseg = enc_segments(nbits);
+    return launch_wah_encode(b, st);
 }
 
 extern "C" int csbfs_wah_decode_or(const uint64_t *words, int64_t n_words, int64_t nbits,

@@ -95,6 +95,11 @@ def test_host_side_argument_checks(lib):
     assert lib.csbfs_wah_capacity(-1) == -1
     assert lib.csbfs_wah_workspace_bytes(1 << 20) > 0
     assert lib.csbfs_wah_encode(None, None, 64, None, 0, None, None, 0, None) == -1
+    lib.csbfs_wah_noalloc_max_bits.restype = ctypes.c_int64
+    assert lib.csbfs_wah_noalloc_max_bits() > 4 * 10**9
+    lib.csbfs_wah_encode_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.csbfs_wah_encode_noalloc(None, None, 64, None, 2, None, None) == -1
     assert lib.csbfs_wah_decode_or(None, 1, 64, None, None, None, 0, None) == -1
 
 
