@@ -65,8 +65,28 @@ struct BigItem {
     int32_t end;
 };
 
+// Block marks: one uint32 per 64 words (4096 vertices) of an n-bit map
+// tells whether a level's bitmap may have a vertex there, so that the
+// encoder, the top-down view scan and the clearing of old state skip the
+// blocks that are all zero. Marked with plain stores of 1 (idempotent; a
+// stale read only costs a repeated store). Block of global word q: q >> 6;
+// view (r, j) word q holds bits of global word j * W + q, the index of that
+// word within processor r's views, so one index serves both.
+constexpr int kMarkShift = 6;
+struct BlockMarks {
+    uint32_t *m;  // [ceil(n / 4096)]
+    __device__ __forceinline__ void mark_word(int64_t q) const {
+        const int64_t k = q >> kMarkShift;
+        if (!m[k]) m[k] = 1u;
+    }
+    __device__ __forceinline__ bool word_marked(int64_t q) const { return m[q >> kMarkShift] != 0; }
+};
+
 struct ExpandArgs {
     const uint64_t *view;
+    uint64_t *view_clear;      // the same views: the push zeroes each non-zero word it takes
+    BlockMarks marks_next;     // blocks of the vertices this expansion discovers
+    BlockMarks marks_view;     // blocks of the frontier being expanded (its view words)
     int64_t rank_words;        // view words per processor: P * W
     const int32_t *row_ptr;
     const int64_t *col_base;
@@ -110,7 +130,10 @@ __device__ __forceinline__ void relax_batch(const ExpandArgs &a, const int64_t (
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const uint64_t bit = 1ull << (v[k] & 63);
-            if (!(w[k] & bit)) atomicOr((unsigned long long *)&a.N[v[k] >> 6], (unsigned long long)bit);
+            if (!(w[k] & bit)) {
+                atomicOr((unsigned long long *)&a.N[v[k] >> 6], (unsigned long long)bit);
+                a.marks_next.mark_word(v[k] >> 6);
+            }
         }
     } else {
         uint64_t pw[U];
@@ -129,8 +152,10 @@ __device__ __forceinline__ void relax_batch(const ExpandArgs &a, const int64_t (
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             if (old[k] < u[k]) atomicMax(&a.parent[v[k]], u[k]);
-            if (old[k] < 0)
+            if (old[k] < 0) {
                 atomicOr((unsigned long long *)&a.N[v[k] >> 6], (unsigned long long)(1ull << (v[k] & 63)));
+                a.marks_next.mark_word(v[k] >> 6);
+            }
         }
     }
 }
@@ -140,11 +165,12 @@ __device__ __forceinline__ void relax_batch(const ExpandArgs &a, const int64_t (
 // longer than kBigRow go to the chunk queue (one wave-aggregated
 // reservation); the remaining edges of the 64 sources are spread evenly over
 // the lanes, kUnroll edges per lane per step.
-// The view word of this lane in tile `tile` of processor r (0 past the end).
+// The view word of this lane in tile `tile` of processor r (0 past the end,
+// and 0 without a load where the frontier's block mark is clear).
 __device__ __forceinline__ uint64_t tile_word(const ExpandArgs &a, int32_t r, int64_t tile) {
     const int lane = threadIdx.x & 63;
     const int64_t wl = tile * a.tile_words + lane;
-    const bool in = lane < a.tile_words && wl < a.rank_words;
+    const bool in = lane < a.tile_words && wl < a.rank_words && a.marks_view.word_marked(wl);
     return in ? a.view[(int64_t)r * a.rank_words + wl] : 0;
 }
 
@@ -153,6 +179,9 @@ __device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int6
                                             unsigned long long &edges) {
     const int lane = threadIdx.x & 63;
     const int64_t w0 = (int64_t)r * a.rank_words + tile * a.tile_words;  // word of lane 0
+    // the push reads each view word once: zero it for the next level's
+    // decode (the dense evaluation's pull still reads the views after this)
+    if (!kDense && bits) a.view_clear[w0 + lane] = 0;
     const int cnt = __popcll(bits);
     const int incl_b = wave_incl_scan_i32(cnt);
     const int tot_b = __shfl(incl_b, 63, 64);
@@ -320,6 +349,7 @@ __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
 
 struct PullArgs {
     uint64_t *N;           // vertices discovered in this level
+    BlockMarks marks_next;  // their blocks (bottom-up)
     const uint64_t *pi;
     const uint64_t *live;  // vertices with at least one adjacency entry
     const uint64_t *view;
@@ -466,6 +496,7 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
                 const unsigned long long fb = found_bits[wid][lane];
                 if (fb) {
                     a.N[wq] |= fb;
+                    a.marks_next.mark_word(wq);
                     found_bits[wid][lane] = 0;
                 }
             }
@@ -562,15 +593,18 @@ __device__ __forceinline__ unsigned long long *update_sums() {
 
 // The update of Alg. 3 (t = the new vertices, pi = pi or t, f = t, levels
 // of the new vertices) done inside the encoder of f. The words the encoder
-// stages are N_cur, filled by the last expansion. Beside the look-back, the
-// workgroup of stream i -> j clears view (j, i) at the segment's words (the
-// view that stream decodes into) and, with the other p - 1 workgroups of
-// sender i's segment, takes the segment's 8-word steps round-robin: pi |= f,
-// the other copy N_old (the previous frontier) cleared for the next
-// expansion, then level and adjacency-entry count of every new vertex (lane
-// = vertex; all masked loads of a step in flight before any is summed).
-// Each word is taken by one lane, and no workgroup of this launch reads pi
-// or N_old, so the plain read-modify-writes need no atomics.
+// stages are N_cur, filled by the last expansion; segments whose mark says
+// N_cur is zero there are not staged at all (the encoder's clean path).
+// Beside the look-back, the workgroup of stream i -> j clears view (j, i)
+// at the segment's words (the view that stream decodes into) if they can
+// hold bits of f^(k-1) that the last expansion did not zero, and, with the
+// other p - 1 workgroups of sender i's segment, takes the segment's 8-word
+// steps round-robin: pi |= f, the other copy N_old (the previous frontier)
+// cleared for the next expansion, then level and adjacency-entry count of
+// every new vertex (lane = vertex; all masked loads of a step in flight
+// before any is summed). Each word is taken by one lane, and no workgroup
+// of this launch reads pi or N_old, so the plain read-modify-writes need no
+// atomics.
 struct FrontierHook {
     const uint64_t *N_cur;   // f^k: vertices discovered while expanding f^(k-1)
     uint64_t *N_old;         // f^(k-1): cleared here, refilled by the next expansion
@@ -579,13 +613,35 @@ struct FrontierHook {
     int32_t *level;
     const int32_t *deg;
     unsigned long long *part;  // [streams * nseg][2] per-workgroup sums
+    BlockMarks mark_cur;       // blocks where f^k may have a vertex
+    BlockMarks mark_old;       // blocks where f^(k-1) may have had one
     int64_t W;
     int64_t seg_words;  // bitmap words per encoder segment
     int32_t P;
     int32_t lvl;  // k
+    int32_t clear_views;  // the expansion of f^(k-1) left its view words in place
 
     __device__ __forceinline__ uint64_t load(const WahBatch &, int64_t, int64_t i, int64_t w) const {
         return N_cur[i * W + w];
+    }
+    __device__ __forceinline__ int64_t seg_end(const WahBatch &b, int64_t seg) const {
+        const int64_t q0 = seg * seg_words;
+        return seg == b.nseg - 1 ? W : (q0 + seg_words < W ? q0 + seg_words : W);
+    }
+    // the whole workgroup: is every block of sender i's segment unmarked?
+    __device__ __forceinline__ bool clean(const WahBatch &b, int64_t seg, const StreamIdx &x) const {
+        const int64_t g0 = x.i * W + seg * seg_words, g1 = x.i * W + seg_end(b, seg);
+        const int64_t k0 = g0 >> kMarkShift, k1 = (g1 - 1) >> kMarkShift;
+        int any = 0;
+        for (int64_t k = k0 + threadIdx.x; k <= k1; k += blockDim.x) any |= mark_cur.m[k] != 0;
+        return !__syncthreads_or(any);
+    }
+    // thread 0: is the group before the segment (its last bits) surely zero?
+    __device__ __forceinline__ bool prev_clean(const WahBatch &b, int64_t seg, const StreamIdx &x) const {
+        if (seg == 0) return false;
+        const int64_t gx = seg * (seg_words * 64 / kGroupBits) - 1;  // the segment's first group, minus one
+        const int64_t w0 = x.i * W + (gx * kGroupBits >> 6), w1 = x.i * W + ((gx * kGroupBits + kGroupBits - 1) >> 6);
+        return !mark_cur.word_marked(w0) && !mark_cur.word_marked(w1);
     }
     __device__ __forceinline__ void init() {
         if (threadIdx.x < 2) update_sums()[threadIdx.x] = 0;
@@ -595,10 +651,13 @@ struct FrontierHook {
         const int t = (int)threadIdx.x - 64, nt = (int)blockDim.x - 64;
         const int lane = threadIdx.x & 63;
         const int64_t q0 = seg * seg_words;
-        const int64_t q1 = seg == b.nseg - 1 ? W : (q0 + seg_words < W ? q0 + seg_words : W);
-        uint64_t *vw = view + (x.j * P + x.i) * W;
-        for (int64_t q = q0 + t; q < q1; q += nt) vw[q] = 0;
+        const int64_t q1 = seg_end(b, seg);
         const int64_t base = x.i * W;
+        if (clear_views) {
+            uint64_t *vw = view + (x.j * P + x.i) * W;
+            for (int64_t q = q0 + t; q < q1; q += nt)
+                if (mark_old.word_marked(base + q)) vw[q] = 0;
+        }
         const int64_t nsteps = (q1 - q0 + kUpdWords - 1) / kUpdWords;
         unsigned long long cnt = 0, dsum = 0;
         for (int64_t c = x.j + (int64_t)P * (t >> 6); c < nsteps; c += (int64_t)P * (nt >> 6)) {
@@ -606,12 +665,14 @@ struct FrontierHook {
             const int64_t qk = qa + lane;
             uint64_t tk = 0;
             if (lane < kUpdWords && qk < q1) {
-                tk = N_cur[base + qk];
-                const uint64_t old = N_old[base + qk];
-                if (tk) pi[base + qk] |= tk;
-                if (old) N_old[base + qk] = 0;
+                if (mark_cur.word_marked(base + qk)) {
+                    tk = N_cur[base + qk];
+                    if (tk) pi[base + qk] |= tk;
+                }
+                if (mark_old.word_marked(base + qk) && N_old[base + qk]) N_old[base + qk] = 0;
                 cnt += (unsigned long long)__popcll(tk);
             }
+            if (!__ballot(tk != 0)) continue;
             int32_t d[kUpdWords];
 #pragma unroll
             for (int k = 0; k < kUpdWords; ++k) {
@@ -647,7 +708,9 @@ struct FrontierHook {
 template <int kGpt>
 __global__ __launch_bounds__(kEncThreads) void frontier_encode_kernel(WahBatch b, FrontierHook h,
                                                                       const DirState *st) {
-    if (st->cur == kDirIdle) return;
+    const int32_t d = st->cur;  // the direction f^(k-1) was expanded in
+    if (d == kDirIdle) return;
+    h.clear_views = d != kDirTD;  // the sparse push zeroes the view words it reads
     encode_segment<kGpt>(b, h);
 }
 
@@ -659,6 +722,8 @@ struct ReduceArgs {
     uint32_t *ctrs;                  // [P]: chunk-queue counts, cleared for the expansion
     int32_t P;
     int32_t level;                   // k
+    uint32_t *marks_clear;           // [nmarks]: the marks of f^(k-1), cleared for the next expansion
+    int64_t nmarks;
     DirArgs dir;
 };
 
@@ -678,6 +743,7 @@ __global__ __launch_bounds__(kDecThreads) void search_decode_kernel(WahBatch b, 
         nf = (unsigned long long)block_reduce((long long)nf, SumI64(), 0LL);
         mf = (unsigned long long)block_reduce((long long)mf, SumI64(), 0LL);
         if (threadIdx.x < r.P) r.ctrs[threadIdx.x] = 0;
+        for (int64_t k = threadIdx.x; k < r.nmarks; k += blockDim.x) r.marks_clear[k] = 0;
         if (threadIdx.x == 0) {
             r.total[0] = nf;
             r.total[1] = mf;
@@ -712,6 +778,8 @@ struct SeedArgs {
     int64_t zero_words;
     uint32_t *look;      // encoder look-back words and tickets (any contents in a new workspace)
     int64_t look_words;
+    uint32_t *marks;     // both levels' segment marks [2 * nmarks]
+    int64_t mark_words;
 };
 
 __global__ void seed_fill_kernel(SeedArgs a) {
@@ -719,9 +787,11 @@ __global__ void seed_fill_kernel(SeedArgs a) {
     int64_t top = a.n > a.view_words ? a.n : a.view_words;
     top = top > a.zero_words ? top : a.zero_words;
     top = top > a.look_words ? top : a.look_words;
+    top = top > a.mark_words ? top : a.mark_words;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < top; k += stride) {
         if (k < a.zero_words) a.zero[k] = 0;
         if (k < a.look_words) a.look[k] = 0;
+        if (k < a.mark_words) a.marks[k] = 0;
         if (k < a.n) {
             a.level[k] = -1;
             a.parent[k] = -1;
@@ -738,7 +808,8 @@ __global__ void seed_fill_kernel(SeedArgs a) {
 // f(s) <- s: the source is known to every processor without a message.
 __global__ void seed_root_kernel(SeedArgs a, int64_t root, int64_t R, int64_t W, int32_t P,
                                  unsigned long long *ctl0, unsigned long long *rank0,
-                                 const int32_t *deg, DirState *ds, int32_t *rec0, int32_t dir0) {
+                                 const int32_t *deg, DirState *ds, int32_t *rec0, int32_t dir0,
+                                 BlockMarks marks0) {
     const int64_t own = root / R, rl = root - own * R;
     DirState s;
     s.cur = dir0;
@@ -751,6 +822,7 @@ __global__ void seed_root_kernel(SeedArgs a, int64_t root, int64_t R, int64_t W,
     a.parent[root] = (int32_t)root;
     a.pi[root >> 6] |= 1ull << (root & 63);
     for (int32_t i = 0; i < P; ++i) a.view[((int64_t)i * P + own) * W + (rl >> 6)] |= 1ull << (rl & 63);
+    marks0.mark_word(root >> 6);  // f^0's block, so its views are scanned and later cleared
     ctl0[0] = 1;
     rank0[own] = 1;
 }
@@ -786,7 +858,8 @@ struct SearchLayout {
     uint32_t flags;
     float alpha, beta;
     // byte offsets
-    int64_t pi, nb0, nb1, view, arena, look, look_bytes, chunk_groups, queue, part, dstate, counters,
+    int64_t seg_words, nmarks;  // bitmap words per encoder segment; block marks per level
+    int64_t pi, nb0, nb1, view, arena, look, look_bytes, chunk_groups, queue, part, dstate, marks, counters,
         counters_bytes, total;
 };
 
@@ -805,6 +878,7 @@ struct SearchState {
     LevelCounters lc;
     int32_t *status;
     uint32_t *ctrs;  // [P]: chunk-queue items pushed
+    uint32_t *marks[2];  // block marks by level parity: marks[k & 1] for f^k
 };
 
 constexpr uint32_t kSearchFlags = CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE | CSBFS_FLAG_SPARSE_ONLY |
@@ -834,8 +908,10 @@ int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *
     y.cap = wah_cap(y.R);
     y.enc_gpt = c.segment_groups == 1024 ? 2 : c.segment_groups == 2048 ? 4 : search_enc_gpt(y.R, y.S);
     y.nseg = enc_segments(y.R, y.enc_gpt);
+    y.seg_words = (int64_t)kEncThreads * y.enc_gpt * kGroupBits / 64;
     y.nchunk = dec_chunks(y.R);
     y.words = n / 64;
+    y.nmarks = (y.words + 63) >> kMarkShift;
     y.L = c.max_levels;
     y.arena_slots = (c.flags & CSBFS_FLAG_KEEP_STREAMS) ? y.L + 1 : 1;
     y.queue_cap = big_items_bound(nnz);
@@ -861,6 +937,7 @@ int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *
     y.queue = take((int64_t)sizeof(BigItem) * y.queue_cap);
     y.part = take(16 * y.S * y.nseg);
     y.dstate = take((int64_t)sizeof(DirState));
+    y.marks = take(4 * 2 * y.nmarks);
     // everything a search starts from zero, in one block the seed clears:
     // per-level counters, then the status flag and the queue counts
     const int64_t slots = y.L + 1;
@@ -886,6 +963,8 @@ SearchState bind_workspace(const SearchLayout &y, void *ws) {
     w.queue = (BigItem *)(b + y.queue);
     w.part = (unsigned long long *)(b + y.part);
     w.dstate = (DirState *)(b + y.dstate);
+    w.marks[0] = (uint32_t *)(b + y.marks);
+    w.marks[1] = w.marks[0] + y.nmarks;
     w.counters_mem = b + y.counters;
     const int64_t slots = y.L + 1, P = y.P, S = y.S;
     unsigned long long *c = (unsigned long long *)w.counters_mem;
@@ -989,17 +1068,20 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
     }
     // a0: seed (also clears the counters and the encoder's look-back state)
     SeedArgs sa{level, parent, w.pi, w.nb[0], w.nb[1], w.view, n, words, view_words,
-                (uint32_t *)w.counters_mem, y.counters_bytes / 4, (uint32_t *)w.look, y.look_bytes / 4};
+                (uint32_t *)w.counters_mem, y.counters_bytes / 4, (uint32_t *)w.look, y.look_bytes / 4,
+                w.marks[0], 2 * y.nmarks};
+    auto marks_of = [&](int64_t k) { return BlockMarks{w.marks[k & 1]}; };
     int64_t fill_items = n > view_words ? n : view_words;
     fill_items = fill_items > y.look_bytes / 4 ? fill_items : y.look_bytes / 4;
     hipLaunchKernelGGL(seed_fill_kernel, dim3(grid_for(fill_items, 256, 8192)), dim3(256), 0, st, sa);
     CSBFS_HIP(hipGetLastError());
     hipLaunchKernelGGL(seed_root_kernel, dim3(1), dim3(1), 0, st, sa, root, R, W, (int32_t)P, w.lc.ctl, w.lc.rank,
-                       (const int32_t *)g->deg, w.dstate, w.lc.dir, dir0);
+                       (const int32_t *)g->deg, w.dstate, w.lc.dir, dir0, marks_of(0));
     CSBFS_HIP(hipGetLastError());
 
     ExpandArgs ea{};
     ea.view = w.view;
+    ea.view_clear = w.view;
     ea.rank_words = P * W;
     ea.row_ptr = g->row_ptr;
     ea.col_base = g->col_base;
@@ -1084,8 +1166,8 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
             wb.n_words = w.lc.words + sj * S;
             wb.stat_sieved_bits = w.lc.sbits + sj * S;
             wb.stat_unsieved_words = w.lc.uwords + sj * P;
-            FrontierHook fh{w.nb[j & 1], w.nb[(j + 1) & 1], w.pi, w.view, level, g->deg, w.part, W,
-                            (int64_t)kEncThreads * y.enc_gpt * kGroupBits / 64, (int32_t)P, (int32_t)j};
+            FrontierHook fh{w.nb[j & 1], w.nb[(j + 1) & 1], w.pi, w.view, level, g->deg, w.part,
+                            marks_of(j), marks_of(j + 1), W, y.seg_words, (int32_t)P, (int32_t)j, 1};
             if (y.enc_gpt == 2)
                 hipLaunchKernelGGL(frontier_encode_kernel<2>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
                                    (const DirState *)w.dstate);
@@ -1098,7 +1180,7 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
             // views; a3: reduction of |f^j|, direction of its expansion
             da.rec = w.lc.dir + sj;
             ReduceArgs ra{w.part, S * y.nseg, w.lc.ctl + 2 * sj, mb.dev ? mb.dev + (j & 1) : nullptr, w.ctrs,
-                          (int32_t)P, (int32_t)j, da};
+                          (int32_t)P, (int32_t)j, w.marks[(j + 1) & 1], y.nmarks, da};
             hipLaunchKernelGGL(search_decode_kernel, dec_grid, dim3(kDecThreads), 0, st, wb, ra);
             CSBFS_HIP(hipGetLastError());
         } else if (ev) {
@@ -1108,6 +1190,10 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
         ea.N = w.nb[(j + 1) & 1];
         pa.N = w.nb[(j + 1) & 1];
         pb.N = w.nb[(j + 1) & 1];
+        ea.marks_next = marks_of(j + 1);
+        ea.marks_view = marks_of(j);
+        pa.marks_next = marks_of(j + 1);
+        pb.marks_next = marks_of(j + 1);
         // a1: expand f^j (tile width and direction chosen on the device)
         ea.edges = w.lc.edges + sj;
         if (dense) {

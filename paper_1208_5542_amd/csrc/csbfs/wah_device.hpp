@@ -181,10 +181,33 @@ struct PlainWords {
     __device__ __forceinline__ uint64_t load(const WahBatch &b, int64_t r, int64_t i, int64_t w) const {
         return b.bits_base[r * b.bits_plane_stride + i * b.words_per_piece + w];
     }
+    // no segment is known to be all zero without reading it
+    __device__ __forceinline__ bool clean(const WahBatch &, int64_t, const StreamIdx &) const { return false; }
+    __device__ __forceinline__ bool prev_clean(const WahBatch &, int64_t, const StreamIdx &) const { return false; }
     __device__ __forceinline__ void init() {}
     __device__ __forceinline__ void side(const WahBatch &, int64_t, int64_t, const StreamIdx &) {}
     __device__ __forceinline__ void finish(const WahBatch &, int64_t, int64_t) {}
 };
+
+// Class of group gx read straight from memory (sieved or not): the clean
+// segment's look at the group before it.
+template <class Hook>
+__device__ int group_class_direct(const WahBatch &b, const StreamIdx &x, int64_t gx, const Hook &h, bool sieved) {
+    const uint64_t *mask = sieved && b.mask_base ? b.mask_base + (x.j * b.P + x.i) * b.words_per_piece : nullptr;
+    const int tail = (int)(b.nbits & 63);
+    auto word = [&](int64_t w) {
+        uint64_t v = h.load(b, x.r, x.i, w);
+        if (tail && w == b.words_per_piece - 1) v &= (1ull << tail) - 1;
+        if (mask && v) v &= mask[w];
+        return v;
+    };
+    const int64_t sb = gx * kGroupBits;
+    const int64_t w0 = sb >> 6;
+    const int off = (int)(sb & 63);
+    uint64_t v = word(w0) >> off;
+    if (off > 1) v |= word(w0 + 1) << (64 - off);
+    return group_class(v & kMask63);
+}
 
 // r trailing bits, right-aligned, first bit most significant.
 __device__ __forceinline__ uint64_t active_word(const uint64_t *arr, const SegGeom &g) {
@@ -311,7 +334,13 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook) {
     const StreamIdx x = stream_idx(s, b.P);
     const bool unsieved = b.stat_unsieved_words && x.i == x.j;
     const SegGeom g = seg_geom<kSeg>(b, seg);
-    stage(b, s, g, sw, unsieved ? su : nullptr, hook);
+    // A clean segment (all zero, known from the hook without reading it) is
+    // a run of 0-groups: it starts a word only at group 0 or after a group
+    // of another class, which it reads from memory if the segment before is
+    // not clean too. Nothing is staged.
+    const bool clean = hook.clean(b, seg, x);
+    int clean_uflag = 0;
+    if (!clean) stage(b, s, g, sw, unsieved ? su : nullptr, hook);
 
     const int64_t xa = g.x0 + (int64_t)threadIdx.x * kGpt;
     const int64_t xb = xa + kGpt < g.x1 ? xa + kGpt : g.x1;
@@ -321,7 +350,18 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook) {
     long long ones = 0;
 #pragma unroll
     for (int k = 0; k < kGpt; ++k) cls[k] = -1;
-    if (xa < g.x1) {
+    if (clean) {
+        if (threadIdx.x == 0 && g.x0 < g.x1) {
+            const bool first = seg == 0;
+            const bool look = !first && !hook.prev_clean(b, seg, x);
+            if (first || (look && group_class_direct(b, x, g.x0 - 1, hook, true) != 0)) {
+                cls[0] = 0;
+                nflag = 1;
+            }
+            if (unsieved && (first || (look && group_class_direct(b, x, g.x0 - 1, hook, false) != 0)))
+                clean_uflag = 1;
+        }
+    } else if (xa < g.x1) {
         int prev = xa > 0 ? group_class(group_bits(sw, xa - 1, g.wlo)) : -1;
         for (int k = 0; k < kGpt; ++k) {
             const int64_t gx = xa + k;
@@ -349,9 +389,17 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook) {
     __syncthreads();
 
     unsigned long long *look = b.look + s * b.nseg;
+    // a clean segment that starts no word and is not the last writes nothing:
+    // it publishes its (empty) aggregate and needs no prefix
+    const bool quiet = clean && seg_words == 0 && !g.last && seg > 0;
     if (threadIdx.x < 64) {
         const uint64_t mine = lb_value(seg_words, seg_words ? starts[seg_words - 1] : 0, sh_last_cls);
-        if (seg == 0) {
+        if (quiet) {
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(&look[seg], mine | kLbAgg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sh_prefix = 0;
+            }
+        } else if (seg == 0) {
             if (threadIdx.x == 0) {
                 __hip_atomic_store(&look[0], mine | kLbInc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sh_prefix = 0;
@@ -402,7 +450,7 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook) {
         }
         if (g.last) {
             int64_t total = offset + seg_words;
-            if (g.r > 0 && fits) out[total++] = active_word(sw, g);
+            if (g.r > 0 && fits) out[total++] = clean ? 0ull : active_word(sw, g);
             b.n_words[s] = fits ? total : 0;
         }
     }
@@ -411,13 +459,13 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook) {
     long long tot = block_reduce(ones, SumI64(), 0LL);
     int ucnt = 0;
     if (unsieved) {
-        int uf = 0, ufirst;
+        int uf = clean_uflag, ufirst;
         long long uones;
-        if (xa < g.x1) classify(su, g, xa, xb, uf, ufirst, uones);
+        if (!clean && xa < g.x1) classify(su, g, xa, xb, uf, ufirst, uones);
         ucnt = block_reduce(uf, SumI32(), 0);
     }
     if (threadIdx.x == 0) {
-        if (g.last && g.r > 0) tot += __popcll(active_word(sw, g));
+        if (g.last && g.r > 0 && !clean) tot += __popcll(active_word(sw, g));
         if (b.stat_sieved_bits && tot) atomicAdd(&b.stat_sieved_bits[s], (unsigned long long)tot);
         if (unsieved) {
             const int words = ucnt + (g.last && g.r > 0 ? 1 : 0);

@@ -1,4 +1,6 @@
 """Helpers shared by the GPU tests (no method arithmetic here)."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -30,5 +32,8 @@ def u64(t: torch.Tensor) -> np.ndarray:
     return t.detach().cpu().numpy().astype(np.int64).view(np.uint64)
 
 
+_T0 = time.perf_counter()
+
+
 def log(msg: str):
-    print(msg, flush=True)
+    print(f"[{time.perf_counter() - _T0:7.1f}s] {msg}", flush=True)
