@@ -285,16 +285,23 @@ def serving_section(args):
         g = csbfs.Graph(torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), n, 4)
         roots = [int(r) for r in inputs.pick_roots(n, src, dst, 128, inputs.graph_seed(scale) + 3)]
         del src, dst
-        # traversed tuples per root (TEPS numerator), from one search each
+        # traversed tuples per root (TEPS numerator) and the time of the
+        # same search on the single-root engine alone, from one search each
         eng = csbfs.Engine(g, max_levels=256)
         level = torch.empty(n, dtype=torch.int32, device="cuda")
         parent = torch.empty(n, dtype=torch.int32, device="cuda")
-        m = []
+        eng.bfs(roots[0], level, parent, with_stats=False)
+        stream = torch.cuda.current_stream()
+        m, ts = [], []
         for r in roots:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             eng.bfs(r, level, parent, with_stats=False)
+            e1.record(stream)
             m.append(g.traversed_tuples(level))
+            ts.append(e0.elapsed_time(e1) / 1e3)
         del eng, level, parent
-        pool.append(dict(name=name, n=n, g=g, roots=roots, m=m))
+        pool.append(dict(name=name, n=n, g=g, roots=roots, m=m, t_single=ts))
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     log(f"[bench] serving: pool of {len(pool)} graphs ready in {time.perf_counter() - t0:.1f}s")
@@ -324,6 +331,7 @@ def serving_section(args):
     lat = np.array([i["t_done"] - i["t_submit"] for i in infos]) * 1e3
     span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
     m_tot = sum(pool[gi]["m"][ri] for gi, ri in meta)
+    t_single = sum(pool[gi]["t_single"][ri] for gi, ri in meta)
     per_graph = {}
     for (gi, _), l in zip(meta, lat):
         per_graph.setdefault(pool[gi]["name"], []).append(l)
@@ -336,11 +344,18 @@ def serving_section(args):
                        "p99": round(float(np.percentile(lat, 99)), 3),
                        "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
         "latency_p50_ms_by_graph": {k: round(float(np.percentile(v, 50)), 3) for k, v in per_graph.items()},
+        "latency_p99_ms_by_graph": {k: round(float(np.percentile(v, 99)), 3) for k, v in per_graph.items()},
         "gteps": round(m_tot / span / 1e9, 4),
+        "single_root_gteps_same_requests": round(m_tot / t_single / 1e9, 4),
+        "single_root_note": "the same requests searched one after another on the single-root engine "
+                            "(sum of tuples / sum of search times)",
         "mean_batch": round(float(np.mean([i["batch_size"] for i in infos])), 2),
+        "batched_fraction": round(float(np.mean([i["batched"] for i in infos])), 3),
     }
     log(f"[bench] serving: {out['achieved_qps']} qps, p50 {out['latency_ms']['p50']} ms, "
-        f"p99 {out['latency_ms']['p99']} ms, {out['gteps']} GTEPS, mean batch {out['mean_batch']}")
+        f"p99 {out['latency_ms']['p99']} ms, {out['gteps']} GTEPS (single-root alone "
+        f"{out['single_root_gteps_same_requests']}), mean batch {out['mean_batch']}, "
+        f"batched {out['batched_fraction']}")
     del pool
     torch.cuda.empty_cache()
     return out

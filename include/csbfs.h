@@ -393,23 +393,29 @@ int csbfs_engine_copy_stream(const csbfs_engine *e, int32_t k, int32_t i, int32_
 
 /*
  * A batched search runs Algorithm 3 for up to 64 roots together. Every
- * vertex carries a 64-bit visit mask (bit r: reached by root r's search);
- * the expansion pushes a source's mask of frontier roots along each edge
- * once. Each root keeps its own frontier bitmap (one bit-plane per root),
- * so every root's messages are exactly those of its single-root search:
- * p x p streams per root and level, sieved by the same directory and
- * WAH-64 compressed, all in one launch per step. Levels only (no parents).
+ * vertex carries a 64-bit visit mask (bit r: reached by root r's search).
+ * A top-down level pushes a source's mask of frontier roots along each edge
+ * once; a bottom-up level lets every vertex still missing some roots OR its
+ * neighbours' frontier masks until all of them are found (the direction-
+ * optimizing search the paper names as future work, Sec. VIII, over the
+ * union of the roots' frontiers), chosen per level on the device. Each root
+ * keeps its own frontier bitmap (one bit-plane per root), so every root's
+ * messages are exactly those of its single-root search: p x p streams per
+ * root and level, sieved by the same directory and WAH-64 compressed, all
+ * in one launch per step. Levels only (no parents).
  */
 typedef struct csbfs_batch_engine csbfs_batch_engine;
 
 /* Workspace for batches of up to max_roots (1..64) roots and max_levels
  * levels of counters (1..65536). Flags: CSBFS_FLAG_TIMING,
- * CSBFS_FLAG_KEEP_STREAMS, CSBFS_FLAG_NO_SIEVE. The graph must outlive the
- * engine. Blocking. Errors: EINVAL, EHIP. */
+ * CSBFS_FLAG_KEEP_STREAMS, CSBFS_FLAG_NO_SIEVE, and CSBFS_FLAG_SPARSE_ONLY
+ * or CSBFS_FLAG_BOTTOM_UP_ONLY to force one evaluation at every level (the
+ * results are identical). The graph must outlive the engine. Blocking.
+ * Errors: EINVAL, EHIP. */
 int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots, int32_t max_levels,
                               uint32_t flags, csbfs_batch_engine **out);
 
-/* Release a batch engine. NULL is accepted. Blocking. */
+/* Release a batch engine (hipFree waits for work still using it). NULL is accepted. */
 int csbfs_batch_engine_free(csbfs_batch_engine *e);
 
 /*
@@ -421,7 +427,9 @@ int csbfs_batch_engine_free(csbfs_batch_engine *e);
  *   stats   host csbfs_level_stats[stats_cap] or NULL: per level, summed
  *           over the roots whose frontier at that level is not empty
  *           (frontier, bits and bytes as for csbfs_bfs; edges counts the
- *           adjacency entries the batch scanned once for all its roots).
+ *           adjacency entries the batch read once for all its roots: the
+ *           rows of the union frontier top-down, the entries read before
+ *           every missing root was found bottom-up; direction as used).
  *   n_levels host: max over roots of (max level + 1).
  * Blocking. Errors: EINVAL, ERANGE (a root outside [0, n)), ECORRUPT, EHIP.
  */
@@ -452,16 +460,22 @@ int64_t csbfs_batch_engine_bytes(const csbfs_graph *g, int32_t max_roots, int32_
 /*
  * A server answers breadth-first queries (graph, root) -> level[] over graphs
  * registered with it (built once and resident in HBM). Requests wait in one
- * queue; each of `slots` worker threads owns a HIP stream and, whenever it is
- * free, takes the oldest waiting request together with up to max_batch - 1
- * more waiting requests for the same graph and answers them with one batched
- * search (csbfs_batch_bfs), so requests that arrive while others run are
- * admitted as soon as a slot frees up, and the slots' batches overlap on the
- * device. Batch engines are kept per (slot, graph) and admitted under an HBM
- * budget: a batch starts only when its engine and result buffer fit next to
- * the engines already held (idle engines are released, least recently used
- * first, to make room). Every result equals that of a search from the same
- * root alone (levels are exact; no parents are returned).
+ * queue per graph; each of `slots` worker threads owns a HIP stream and,
+ * whenever it is free, serves the graph whose oldest request has the
+ * highest response ratio ((waiting time + expected service time) / expected
+ * service time, from the graph's measured search times: short searches go
+ * first and long waits are not starved). It takes up to max_batch of that
+ * graph's waiting requests and answers them either one by one with the
+ * direction-optimizing single-root search or together with one batched
+ * search (csbfs_batch_bfs), whichever the graph's measured costs say is
+ * cheaper for that many roots. Requests that arrive while others run are
+ * admitted as soon as a slot frees up, and the slots' searches overlap on
+ * the device. Per (slot, graph) one device block (batched engine, result
+ * buffer, single-root workspace) is admitted under an HBM budget; blocks
+ * come from the stream-ordered allocator and idle ones are released, least
+ * recently used first, to make room, without synchronizing the device.
+ * Every result equals that of a search from the same root alone (levels
+ * are exact; no parents are returned).
  */
 typedef struct csbfs_server csbfs_server;
 
@@ -480,9 +494,10 @@ typedef struct csbfs_request_info {
     int32_t graph_id;
     int32_t status;      /* CSBFS_OK or a negative status of the batch it ran in */
     int32_t n_levels;    /* max level + 1 of this root's search */
-    int32_t batch_size;  /* requests answered by the same batched search */
+    int32_t batch_size;  /* requests taken together by one worker (one batched search, or
+                            single-root searches one after the other) */
     int32_t slot;
-    int32_t reserved;
+    int32_t batched;     /* 1: answered by a batched search; 0: by a single-root search */
     double t_submit;
     double t_start;      /* its batch started */
     double t_done;       /* its levels were in place */
@@ -499,10 +514,14 @@ int csbfs_server_add_graph(csbfs_server *s, const csbfs_graph *g, int32_t *graph
 /*
  * Queue a query. level_out: device int32[n of the graph] that receives the
  * levels (-1 unreachable), or NULL for no copy-out; the caller keeps it valid
- * until the request is done. Non-blocking; thread-safe. Errors: EINVAL
- * (stopped server, unknown graph), ERANGE (root outside [0, n)).
+ * until the request is done. Ordering: the server writes level_out only
+ * after all work the caller enqueued on `stream` (NULL: the null stream)
+ * before this call (an event recorded on `stream` here, awaited by the
+ * worker's stream), and the write is complete when csbfs_server_wait
+ * returns for this request. Non-blocking; thread-safe. Errors: EINVAL
+ * (stopped server, unknown graph), ERANGE (root outside [0, n)), EHIP.
  */
-int csbfs_server_submit(csbfs_server *s, int32_t graph_id, int64_t root, int32_t *level_out,
+int csbfs_server_submit(csbfs_server *s, int32_t graph_id, int64_t root, int32_t *level_out, void *stream,
                         int64_t *request_id);
 
 /* Block until the request is done and return its outcome (once per id).
@@ -512,7 +531,11 @@ int csbfs_server_wait(csbfs_server *s, int64_t request_id, csbfs_request_info *i
 /* Block until no request is waiting or running. */
 int csbfs_server_drain(csbfs_server *s);
 
-/* Device bytes currently held by the server's engines and buffers. */
+/* Device bytes of one (slot, graph) block of a registered graph (batched
+ * engine, result buffer, single-root workspace, parent scratch), or -1. */
+int64_t csbfs_server_graph_bytes(const csbfs_server *s, int32_t graph_id);
+
+/* Device bytes currently held by the server's blocks. */
 int64_t csbfs_server_bytes_held(const csbfs_server *s);
 
 /* Drain, stop the workers and release everything. NULL is accepted. */

@@ -68,11 +68,11 @@ class ServerConfig(ctypes.Structure):
 class RequestInfo(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("root", ctypes.c_int64), ("graph_id", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("batch_size", ctypes.c_int32),
-                ("slot", ctypes.c_int32), ("reserved", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("slot", ctypes.c_int32), ("batched", ctypes.c_int32), ("t_submit", ctypes.c_double),
                 ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
 
     def as_dict(self) -> dict:
-        return {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "reserved"}
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
 def lib():
@@ -123,10 +123,11 @@ def lib():
         "csbfs_batch_engine_bytes": ([vp, i32, i32, u32], i64),
         "csbfs_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], ctypes.c_int),
         "csbfs_server_add_graph": ([vp, vp, ctypes.POINTER(i32)], ctypes.c_int),
-        "csbfs_server_submit": ([vp, i32, i64, vp, ctypes.POINTER(i64)], ctypes.c_int),
+        "csbfs_server_submit": ([vp, i32, i64, vp, vp, ctypes.POINTER(i64)], ctypes.c_int),
         "csbfs_server_wait": ([vp, i64, ctypes.POINTER(RequestInfo)], ctypes.c_int),
         "csbfs_server_drain": ([vp], ctypes.c_int),
         "csbfs_server_bytes_held": ([vp], i64),
+        "csbfs_server_graph_bytes": ([vp, i32], i64),
         "csbfs_server_free": ([vp], ctypes.c_int),
         "csbfs_wah_capacity": ([i64], i64),
         "csbfs_wah_workspace_bytes": ([i64], sz),
@@ -471,12 +472,15 @@ class Server:
         self.graphs.append(graph)
         return int(gid.value)
 
-    def submit(self, graph_id: int, root: int, out: torch.Tensor | None = None) -> int:
-        """Queue a query; `out` (device int32[n]) receives the levels."""
+    def submit(self, graph_id: int, root: int, out: torch.Tensor | None = None, stream=None) -> int:
+        """Queue a query; `out` (device int32[n]) receives the levels, after
+        the work already queued on `stream` (default: torch's current
+        stream)."""
         if out is not None:
             assert out.dtype == torch.int32 and out.numel() == self.graphs[graph_id].n
         rid = ctypes.c_int64()
-        _check(lib().csbfs_server_submit(self._h, graph_id, int(root), _ptr(out), ctypes.byref(rid)),
+        _check(lib().csbfs_server_submit(self._h, graph_id, int(root), _ptr(out),
+                                         _stream(stream) if out is not None else None, ctypes.byref(rid)),
                "csbfs_server_submit")
         return int(rid.value)
 
@@ -490,6 +494,10 @@ class Server:
 
     def bytes_held(self) -> int:
         return int(lib().csbfs_server_bytes_held(self._h))
+
+    def graph_bytes(self, graph_id: int) -> int:
+        """Device bytes of one (slot, graph) block of a registered graph."""
+        return int(lib().csbfs_server_graph_bytes(self._h, graph_id))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -7,14 +7,26 @@
 // own frontier bitmap: plane r of `f` holds f_r, and plane r of the views
 // holds the pieces P_i received for root r. One level:
 //
-//   expand   every view word position (i, j, q) is read in all planes at
-//            once (lane = root) and transposed with ballots into the masks of
-//            its 64 sources (lane = source); a source's mask travels along
-//            its row of block (i, j) once, for all its roots: nx[v] |= m &
-//            ~vis[v]. Long rows go to per-processor chunk queues.
-//   update   new = nx & ~vis; vis |= new; level[r][v] = k + 1 for each new
-//            bit r; the new masks are transposed back into the planes of
-//            f^{k+1}, and per-root frontier sizes are reduced.
+//   expand   top-down: every view word position (i, j, q) is read in all
+//            planes at once (lane = root) and transposed with ballots into
+//            the masks of its 64 sources (lane = source); a source's mask
+//            travels along its row of block (i, j) once, for all its roots:
+//            nx[v] |= m & ~vis[v]. Long rows go to per-processor chunk queues.
+//            bottom-up: every vertex v still missing some roots whose
+//            frontier is not empty reads its merged row and ORs its
+//            neighbours' frontier masks fm[u] (bit r: u is in root r's
+//            frontier) until every missing root is found or the row ends;
+//            nx[v] = the roots found (one writer per vertex, no atomics). A
+//            neighbour u of v in R_i has V_{i,j}[u] = 1 (Eq. dir-vec), so
+//            u's bit in P_i's view equals its frontier bit (Lemma 1): the
+//            masks stand for the views, which this level then clears.
+//            Chosen per level on the device by Beamer's rule over the union
+//            of the roots' frontiers, as in the single-root search.
+//   update   new = nx & ~vis; vis |= new; fm[v] = new; level[r][v] = k + 1
+//            for each new bit r; the new masks are transposed back into the
+//            planes of f^{k+1}; per-root frontier sizes and the direction
+//            rule's sums (union frontier, its adjacency entries, entries of
+//            vertices still missing a root) are reduced.
 //   messages plane r of f^{k+1} is sieved, WAH-64 compressed, exchanged and
 //            decoded exactly as in the single-root search (wah.hip, one
 //            launch for all planes), so every root's streams equal those of
@@ -22,6 +34,7 @@
 //
 // Levels only: the (select, max) parents would need one 32-bit slot per
 // (vertex, root) and a max-reduction per root and edge.
+#include <memory>
 #include <vector>
 
 #include "device.hpp"
@@ -61,6 +74,7 @@ struct BArgs {
     int32_t *status;
     // nullable: |f^j| summed over the roots; 0 leaves nothing to expand
     const unsigned long long *fcount;
+    const int32_t *dir;  // direction of this level (CSBFS_DIR_*); the push runs if top-down
 };
 
 // Push kBUnroll (target v, root mask m) pairs; loads first, then atomics.
@@ -90,6 +104,7 @@ constexpr int kBRootsPerOp = 64 / kBTile;
 __global__ __launch_bounds__(kBThreads) void bexpand_kernel(BArgs a) {
     __shared__ uint64_t tile[kBThreads / 64][kBTile][kMaxRoots];
     if (a.fcount && *a.fcount == 0) return;
+    if (*a.dir != CSBFS_DIR_TOP_DOWN) return;
     const int lane = threadIdx.x & 63;
     uint64_t(*tw)[kMaxRoots] = tile[threadIdx.x >> 6];
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -197,6 +212,7 @@ __global__ __launch_bounds__(kBThreads) void bexpand_kernel(BArgs a) {
 
 __global__ __launch_bounds__(kBThreads) void bexpand_big_kernel(BArgs a) {
     if (a.fcount && *a.fcount == 0) return;
+    if (*a.dir != CSBFS_DIR_TOP_DOWN) return;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -233,6 +249,126 @@ __global__ __launch_bounds__(kBThreads) void bexpand_big_kernel(BArgs a) {
     block_add<kBThreads / 64>(edges, a.edges);
 }
 
+// ---------------------------------------------------------------- pull ---
+
+constexpr int kBPullUnroll = 2;   // entries per lane step
+// Direction rule of batched searches (Beamer's alpha and beta over the union
+// of the roots' frontiers)
+constexpr float kBatchAlpha = 16.0f, kBatchBeta = 24.0f;
+constexpr int kBPullRounds = 16;  // lane steps before the wave takes over slow lanes
+
+struct BPullArgs {
+    uint64_t *vn;              // [n][2]: visit mask, discovery mask
+    const uint64_t *fm;        // [n]: frontier masks of the level
+    const int64_t *pull_off;   // merged rows (global ids) of every vertex
+    const uint32_t *pull_col;
+    uint64_t *view;            // every view plane, zeroed here (the decode ORs into zeroed views)
+    int64_t view_words;
+    int64_t n;
+    const unsigned long long *rootc;  // [B]: frontier size of each root at this level
+    int32_t B;
+    const int32_t *dir;
+    unsigned long long *edges;
+    const unsigned long long *fcount;
+};
+
+__global__ __launch_bounds__(kBThreads) void bpull_kernel(BPullArgs a) {
+    if (a.fcount && *a.fcount == 0) return;
+    if (*a.dir != CSBFS_DIR_BOTTOM_UP) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = tid; k < a.view_words; k += nthreads) a.view[k] = 0;
+    // roots whose frontier is not empty: only they can find anything
+    const uint64_t active = __ballot(lane < a.B && (!a.rootc || a.rootc[lane] > 0));
+    const int64_t wave = tid >> 6, nwaves = nthreads >> 6;
+    unsigned long long read = 0;
+    for (int64_t v0 = wave * 64; v0 < a.n; v0 += nwaves * 64) {
+        const int64_t v = v0 + lane;
+        uint64_t missing = 0, found = 0;
+        int64_t e = 0, re = 0;
+        if (v < a.n) {
+            missing = active & ~a.vn[2 * v];
+            if (missing) {
+                e = a.pull_off[v];
+                re = a.pull_off[v + 1];
+            }
+        }
+        bool busy = missing && e < re;
+        for (int round = 0; round < kBPullRounds; ++round) {
+            if (busy) {
+                // every lane reads kBPullUnroll entries, positions past the row end
+                // clamped to its last entry and masked out
+                const int32_t nk = re - e < kBPullUnroll ? (int32_t)(re - e) : kBPullUnroll;
+                uint32_t c[kBPullUnroll];
+                uint64_t m[kBPullUnroll];
+#pragma unroll
+                for (int q = 0; q < kBPullUnroll; ++q) c[q] = a.pull_col[e + (q < nk ? q : nk - 1)];
+#pragma unroll
+                for (int q = 0; q < kBPullUnroll; ++q) m[q] = a.fm[c[q]];
+#pragma unroll
+                for (int q = 0; q < kBPullUnroll; ++q)
+                    if (q < nk) found |= m[q] & missing;
+                read += (unsigned long long)nk;
+                e += nk;
+                if (found == missing || e >= re) busy = false;
+            }
+            if (!__ballot(busy)) break;
+        }
+        // rows still being read: the whole wave takes them one at a time
+        uint64_t slow = __ballot(busy);
+        while (slow) {
+            const int Ls = __ffsll((unsigned long long)slow) - 1;
+            slow &= slow - 1;
+            int64_t ee = shfl64(e, Ls);
+            const int64_t rr = shfl64(re, Ls);
+            const uint64_t miss = (uint64_t)shfl64((int64_t)missing, Ls);
+            uint64_t got = (uint64_t)shfl64((int64_t)found, Ls);
+            for (; ee < rr && got != miss; ee += 64) {
+                const int64_t pos = ee + lane;
+                const uint64_t f = pos < rr ? a.fm[a.pull_col[pos]] & miss : 0ull;
+                got |= wave_or64(f);
+                if (lane == 0) read += (unsigned long long)(rr - ee < 64 ? rr - ee : 64);
+            }
+            if (lane == Ls) found = got;
+        }
+        if (found) a.vn[2 * v + 1] = found;  // this lane's vertex: no other writer
+    }
+    for (int d = 32; d > 0; d >>= 1) read += (unsigned long long)shfl64((int64_t)read, lane ^ d);
+    block_add<kBThreads / 64>(read, a.edges);
+}
+
+// Direction state of a batched search, carried from level to level.
+struct BDirState {
+    int32_t cur;              // direction of the level expanded next
+    int32_t force;            // < 0: chosen by the rule; else this direction every level
+    unsigned long long prev;  // union frontier size of the level before
+    unsigned long long sums[3];  // union frontier, its adjacency entries, entries still missing a root
+};
+
+// Beamer's rule over the union of the roots' frontiers (one thread, after the
+// update): top-down turns bottom-up when the frontier's entries times alpha
+// exceed the entries of vertices some root has not reached and the frontier
+// did not shrink; bottom-up turns top-down when the frontier is below
+// n / beta and shrinking. The sums are cleared for the next update.
+__global__ void bdir_kernel(BDirState *st, int32_t *rec, int64_t n, float alpha, float beta) {
+    BDirState s = *st;
+    const unsigned long long nf = s.sums[0], mf = s.sums[1], mu = s.sums[2];
+    int32_t next = s.cur;
+    if (s.force >= 0) {
+        next = s.force;
+    } else if (s.cur == CSBFS_DIR_TOP_DOWN) {
+        if ((double)mf * alpha > (double)mu && nf >= s.prev) next = CSBFS_DIR_BOTTOM_UP;
+    } else if ((double)nf * beta < (double)n && nf < s.prev) {
+        next = CSBFS_DIR_TOP_DOWN;
+    }
+    s.prev = nf;
+    s.cur = next;
+    s.sums[0] = s.sums[1] = s.sums[2] = 0;
+    *st = s;
+    if (rec) *rec = next;
+}
+
 struct BUpdateArgs {
     uint64_t *vn;      // [n][2]
     uint64_t *f;       // [B][n / 64] planes of the new frontier
@@ -245,15 +381,20 @@ struct BUpdateArgs {
     uint32_t *queue_count;           // [P], cleared for the next level
     int32_t P;
     const unsigned long long *fcount;  // as in BArgs: 0 visits nothing
+    uint64_t *fm;                      // [n]: frontier mask of every vertex (written for all)
+    const int32_t *deg;                // [n]: adjacency entries
+    unsigned long long *dsums;         // [3]: union frontier, its entries, entries still missing a root
 };
 
 __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
     __shared__ uint64_t tile[kBThreads / 64][kBTile][kMaxRoots];
     __shared__ unsigned long long cnt[kMaxRoots];
+    __shared__ unsigned long long dsum[3];
     const int lane = threadIdx.x & 63;
     uint64_t(*tw)[kMaxRoots] = tile[threadIdx.x >> 6];
     if (a.fcount && *a.fcount == 0) return;
     if (threadIdx.x < kMaxRoots) cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 3) dsum[threadIdx.x] = 0;
     if (blockIdx.x == 0)
         for (int q = threadIdx.x; q < a.P; q += blockDim.x) a.queue_count[q] = 0;
     __syncthreads();
@@ -264,6 +405,7 @@ __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
     const int t_st = lane % kBTile, r_st = lane / kBTile;
     const int nsteps = (a.B + kBRootsPerOp - 1) / kBRootsPerOp;
     unsigned long long mine = 0;  // lane r: new vertices of root r seen by this wave
+    unsigned long long u_nf = 0, u_mf = 0, u_mu = 0;  // the direction rule's sums, this lane
     for (int64_t tl = wave; tl < ntiles; tl += nwaves) {
         const int64_t q0 = tl * kBTile;
         for (int t = 0; t < kBTile; ++t) {
@@ -277,6 +419,16 @@ __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
                 if (w.y) {
                     nw = w.y & ~w.x;
                     *pv = make_ulonglong2(w.x | nw, 0ull);
+                }
+                a.fm[v] = nw;
+                const uint64_t all = a.B == 64 ? ~0ull : ((1ull << a.B) - 1);
+                if (nw || (all & ~(w.x | nw))) {
+                    const unsigned long long dg = (unsigned long long)a.deg[v];
+                    if (nw) {
+                        u_nf += 1;
+                        u_mf += dg;
+                    }
+                    if (all & ~(w.x | nw)) u_mu += dg;
                 }
                 // lane r collects root r's frontier word: bit b = vertex q*64+b is new for r
                 for (uint64_t it = wave_or64(nw); it; it &= it - 1) {
@@ -299,7 +451,18 @@ __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
         wave_lds_sync();
     }
     if (lane < a.B && mine) atomicAdd(&cnt[lane], mine);
+    for (int d = 32; d > 0; d >>= 1) {
+        u_nf += (unsigned long long)shfl64((int64_t)u_nf, lane ^ d);
+        u_mf += (unsigned long long)shfl64((int64_t)u_mf, lane ^ d);
+        u_mu += (unsigned long long)shfl64((int64_t)u_mu, lane ^ d);
+    }
+    if (lane == 0 && (u_nf | u_mf | u_mu)) {
+        atomicAdd(&dsum[0], u_nf);
+        atomicAdd(&dsum[1], u_mf);
+        atomicAdd(&dsum[2], u_mu);
+    }
     __syncthreads();
+    if (threadIdx.x < 3 && dsum[threadIdx.x]) atomicAdd(&a.dsums[threadIdx.x], dsum[threadIdx.x]);
     if (threadIdx.x < a.B && cnt[threadIdx.x]) atomicAdd(&a.root_count[threadIdx.x], cnt[threadIdx.x]);
     if (threadIdx.x == 0) {
         unsigned long long sum = 0;
@@ -310,6 +473,7 @@ __global__ __launch_bounds__(kBThreads) void bupdate_kernel(BUpdateArgs a) {
 
 struct BSeedArgs {
     uint64_t *vn;      // [n][2]
+    uint64_t *fm;      // [n]
     uint64_t *view;
     int64_t view_words;  // all planes
     int32_t *level;
@@ -321,7 +485,10 @@ __global__ void bseed_fill_kernel(BSeedArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t top = a.view_words > a.level_words ? a.view_words : a.level_words;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < top; k += stride) {
-        if (k < a.n) reinterpret_cast<ulonglong2 *>(a.vn)[k] = make_ulonglong2(0ull, 0ull);
+        if (k < a.n) {
+            reinterpret_cast<ulonglong2 *>(a.vn)[k] = make_ulonglong2(0ull, 0ull);
+            a.fm[k] = 0;
+        }
         if (k < a.view_words) a.view[k] = 0;
         if (k < a.level_words) a.level[k] = -1;
     }
@@ -330,12 +497,22 @@ __global__ void bseed_fill_kernel(BSeedArgs a) {
 // f(s) <- s for every root: known to every processor without a message.
 __global__ void bseed_root_kernel(BSeedArgs a, const int64_t *roots, int32_t B, int64_t R, int64_t W,
                                   int32_t P, int64_t vplane, unsigned long long *root_count0,
-                                  unsigned long long *total0) {
+                                  unsigned long long *total0, BDirState *ds, int32_t dir0, int32_t force,
+                                  int32_t *rec0) {
     const int r = threadIdx.x;
+    if (r == 0) {
+        BDirState d{};
+        d.cur = dir0;
+        d.force = force;
+        d.prev = (unsigned long long)B;
+        *ds = d;
+        if (rec0) *rec0 = dir0;
+    }
     if (r >= B) return;
     const int64_t s = roots[r];
     const int64_t own = s / R, sl = s - own * R;
     atomicOr((unsigned long long *)(a.vn + 2 * s), 1ull << r);
+    atomicOr((unsigned long long *)(a.fm + s), 1ull << r);
     a.level[(int64_t)r * a.n + s] = 0;
     for (int32_t i = 0; i < P; ++i)
         a.view[r * vplane + ((int64_t)i * P + own) * W + (sl >> 6)] = 1ull << (sl & 63);
@@ -354,6 +531,9 @@ struct csbfs_batch_engine {
     uint32_t flags = 0;
     int64_t cap = 0, nseg = 0, nchunk = 0, Smax = 0;
     uint64_t *vn = nullptr, *f = nullptr, *view = nullptr, *arena = nullptr;
+    uint64_t *fm = nullptr;           // [n] frontier mask of every vertex (bottom-up levels)
+    BDirState *dstate = nullptr;
+    int32_t *dirs = nullptr;          // [L + 1] direction used to expand each level
     unsigned long long *look = nullptr;  // encoder look-back words [Smax * nseg]
     uint32_t *enc_ticket = nullptr;      // [kTicketStride * Smax], after look
     size_t look_bytes = 0;
@@ -374,16 +554,19 @@ struct csbfs_batch_engine {
     unsigned long long *host_ctl = nullptr;  // pinned [2]
     hipEvent_t count_ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> events;
-    std::vector<void *> allocs;
+    void *mem = nullptr;     // every device buffer, carved from one block
+    bool owns_mem = false;   // hipMalloc'd here (else the caller's, e.g. the server's pool)
+    bool owns_host = false;  // host_ctl hipHostMalloc'd here
     int32_t last_levels = 0, last_roots = 0;
 };
 
 namespace {
 
+// Releases what the engine itself allocated (hipFree orders itself after
+// work still using the block; a caller-provided block stays the caller's).
 void bengine_release(csbfs_batch_engine *e) {
-    (void)hipDeviceSynchronize();
-    for (void *p : e->allocs) (void)hipFree(p);
-    if (e->host_ctl) (void)hipHostFree(e->host_ctl);
+    if (e->owns_mem && e->mem) (void)hipFree(e->mem);
+    if (e->owns_host && e->host_ctl) (void)hipHostFree(e->host_ctl);
     for (hipEvent_t ev : e->count_ev)
         if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : e->events)
@@ -395,11 +578,17 @@ void bengine_release(csbfs_batch_engine *e) {
 
 namespace {
 
-// Device bytes of every buffer csbfs_batch_engine_create allocates.
+// Device bytes of every buffer of a batch engine; total() is the size of
+// the one block they are carved from (each buffer 256-byte aligned).
 struct BatchSizes {
     int64_t vis, nx, f, view, arena, look, ticket, chunk, queue, qoff, qcount, roots, status, counters;
+    int64_t fm, dstate, dirs;
     int64_t total() const {
-        return vis + nx + f + view + arena + look + ticket + chunk + queue + qoff + qcount + roots + status + counters;
+        int64_t t = 0;
+        for (int64_t b : {vis, f, view, arena, look + ticket, chunk, queue, qoff, qcount, roots, status, counters, fm,
+                          dstate, dirs})
+            t += align_up(b > 0 ? b : 1);
+        return t;
     }
 };
 
@@ -424,6 +613,9 @@ BatchSizes batch_sizes(const csbfs_graph *g, int64_t B, int64_t L, uint32_t flag
     z.roots = 8 * B;
     z.status = 4;
     z.counters = 8 * slots * (1 + B + 1 + Smax + B * P) + 8 * slots * Smax;
+    z.fm = 8 * n;
+    z.dstate = (int64_t)sizeof(BDirState);
+    z.dirs = 4 * slots;
     return z;
 }
 
@@ -435,8 +627,14 @@ extern "C" int64_t csbfs_batch_engine_bytes(const csbfs_graph *g, int32_t max_ro
     return batch_sizes(g, max_roots, max_levels, flags).total();
 }
 
-extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots, int32_t max_levels,
-                                         uint32_t flags, csbfs_batch_engine **out) {
+namespace csbfs {
+
+// A batch engine on a device block `mem` of csbfs_batch_engine_bytes bytes
+// and a pinned two-word host buffer, both owned by the caller (null: the
+// engine allocates them itself). Zeroing runs on `st` and is awaited with a
+// synchronization of `st` alone.
+int batch_engine_make(const csbfs_graph *g, int32_t max_roots, int32_t max_levels, uint32_t flags, void *mem,
+                      unsigned long long *host_ctl, hipStream_t st, csbfs_batch_engine **out) {
     if (!out) return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: out is NULL");
     *out = nullptr;
     if (!g) return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: graph is NULL");
@@ -444,11 +642,14 @@ extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots
         return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: max_roots outside [1, 64]");
     if (max_levels < 1 || max_levels > 65536)
         return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: max_levels outside [1, 65536]");
-    if (flags & ~(CSBFS_FLAG_TIMING | CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE))
+    if (flags & ~(CSBFS_FLAG_TIMING | CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE | CSBFS_FLAG_SPARSE_ONLY |
+                  CSBFS_FLAG_BOTTOM_UP_ONLY))
         return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: unsupported flag");
+    if ((flags & CSBFS_FLAG_SPARSE_ONLY) && (flags & CSBFS_FLAG_BOTTOM_UP_ONLY))
+        return fail(CSBFS_EINVAL, "csbfs_batch_engine_create: SPARSE_ONLY and BOTTOM_UP_ONLY exclude each other");
     int rc = graph_device_check(g);
     if (rc) return rc;
-    csbfs_batch_engine *e = new csbfs_batch_engine();
+    std::unique_ptr<csbfs_batch_engine> e(new csbfs_batch_engine());
     e->g = g;
     e->Bmax = max_roots;
     e->L = max_levels;
@@ -461,46 +662,49 @@ extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots
     const int64_t slots = (int64_t)max_levels + 1;
     std::vector<int64_t> qoff(P + 1, 0);
     for (int64_t r = 0; r < P; ++r) qoff[r + 1] = qoff[r] + g->big_items[r];
-    auto alloc = [&](void **p, size_t bytes) -> int {
-        hipError_t err = hipMalloc(p, bytes > 0 ? bytes : 1);
-        if (err != hipSuccess) return hip_fail(err, "hipMalloc", __FILE__, __LINE__);
-        e->allocs.push_back(*p);
-        return CSBFS_OK;
-    };
-#define BALLOC(ptr, bytes)                                                 \
-    do {                                                                   \
-        void *_p = nullptr;                                                \
-        int _rc = alloc(&_p, (bytes));                                     \
-        if (_rc) {                                                         \
-            bengine_release(e);                                            \
-            return _rc;                                                    \
-        }                                                                  \
-        ptr = reinterpret_cast<decltype(ptr)>(_p);                         \
-    } while (0)
     const BatchSizes z = batch_sizes(g, B, max_levels, flags);
-    BALLOC(e->vn, z.vis);
-    BALLOC(e->f, z.f);
-    BALLOC(e->view, z.view);
-    BALLOC(e->arena, z.arena);
-    // encoder look-back words, then its tickets: zero before the first encode
-    BALLOC(e->look, z.look + z.ticket);
-    e->enc_ticket = reinterpret_cast<uint32_t *>(e->look + e->Smax * e->nseg);
-    BALLOC(e->chunk_groups, z.chunk);
-    BALLOC(e->queue, z.queue);
-    BALLOC(e->qoff, z.qoff);
-    BALLOC(e->qcount, z.qcount);
-    BALLOC(e->roots_dev, z.roots);
-    BALLOC(e->status, z.status);
-    const size_t cnt_bytes = (size_t)z.counters;
-    BALLOC(e->counters_mem, cnt_bytes);
-#undef BALLOC
-    e->counters_bytes = cnt_bytes;
-    e->look_bytes = (size_t)(z.look + z.ticket);
-    const hipError_t zerr = hipMemset(e->look, 0, e->look_bytes);
-    if (zerr != hipSuccess) {
-        bengine_release(e);
-        return hip_fail(zerr, "hipMemset(look)", __FILE__, __LINE__);
+    if (!mem) {
+        CSBFS_HIP(hipMalloc(&e->mem, (size_t)z.total()));
+        e->owns_mem = true;
+    } else {
+        e->mem = mem;
     }
+    if (!host_ctl) {
+        const hipError_t herr = hipHostMalloc((void **)&e->host_ctl, 2 * sizeof(unsigned long long));
+        if (herr != hipSuccess) {
+            e->host_ctl = nullptr;
+            bengine_release(e.release());
+            return hip_fail(herr, "hipHostMalloc", __FILE__, __LINE__);
+        }
+        e->owns_host = true;
+    } else {
+        e->host_ctl = host_ctl;
+    }
+    char *at = (char *)e->mem;
+    auto carve = [&at](int64_t bytes) {
+        void *p = at;
+        at += align_up(bytes > 0 ? bytes : 1);
+        return p;
+    };
+    e->vn = (uint64_t *)carve(z.vis);
+    e->f = (uint64_t *)carve(z.f);
+    e->view = (uint64_t *)carve(z.view);
+    e->arena = (uint64_t *)carve(z.arena);
+    // encoder look-back words, then its tickets: zero before the first encode
+    e->look = (unsigned long long *)carve(z.look + z.ticket);
+    e->enc_ticket = reinterpret_cast<uint32_t *>(e->look + e->Smax * e->nseg);
+    e->chunk_groups = (int64_t *)carve(z.chunk);
+    e->queue = (BItem *)carve(z.queue);
+    e->qoff = (int64_t *)carve(z.qoff);
+    e->qcount = (uint32_t *)carve(z.qcount);
+    e->roots_dev = (int64_t *)carve(z.roots);
+    e->status = (int32_t *)carve(z.status);
+    e->fm = (uint64_t *)carve(z.fm);
+    e->dstate = (BDirState *)carve(z.dstate);
+    e->dirs = (int32_t *)carve(z.dirs);
+    e->counters_mem = carve(z.counters);
+    e->counters_bytes = (size_t)z.counters;
+    e->look_bytes = (size_t)(z.look + z.ticket);
     unsigned long long *c = (unsigned long long *)e->counters_mem;
     e->ctl = c;
     c += slots;
@@ -513,9 +717,11 @@ extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots
     e->uwords = c;
     c += slots * B * P;
     e->words = (int64_t *)c;
-    hipError_t herr = hipMemcpy(e->qoff, qoff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice);
-    if (herr == hipSuccess) herr = hipMemset(e->view, 0, sizeof(uint64_t) * B * P * (n / 64));
-    if (herr == hipSuccess) herr = hipHostMalloc((void **)&e->host_ctl, 2 * sizeof(unsigned long long));
+    hipError_t herr = hipMemsetAsync(e->look, 0, e->look_bytes, st);
+    if (herr == hipSuccess)
+        herr = hipMemcpyAsync(e->qoff, qoff.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice, st);
+    if (herr == hipSuccess) herr = hipMemsetAsync(e->view, 0, sizeof(uint64_t) * B * P * (n / 64), st);
+    if (herr == hipSuccess) herr = hipStreamSynchronize(st);  // qoff is read from host memory
     for (auto &ev : e->count_ev)
         if (herr == hipSuccess) herr = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (herr == hipSuccess && (flags & CSBFS_FLAG_TIMING)) {
@@ -524,11 +730,22 @@ extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots
             if (herr == hipSuccess) herr = hipEventCreate(&ev);
     }
     if (herr != hipSuccess) {
-        bengine_release(e);
+        bengine_release(e.release());
         return hip_fail(herr, "csbfs_batch_engine_create", __FILE__, __LINE__);
     }
-    *out = e;
+    *out = e.release();
     return CSBFS_OK;
+}
+
+void batch_engine_release(csbfs_batch_engine *e) {
+    if (e) bengine_release(e);
+}
+
+}  // namespace csbfs
+
+extern "C" int csbfs_batch_engine_create(const csbfs_graph *g, int32_t max_roots, int32_t max_levels,
+                                         uint32_t flags, csbfs_batch_engine **out) {
+    return batch_engine_make(g, max_roots, max_levels, flags, nullptr, nullptr, nullptr, out);
 }
 
 extern "C" int csbfs_batch_engine_free(csbfs_batch_engine *e) {
@@ -560,12 +777,17 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
     CSBFS_HIP(hipMemsetAsync(e->status, 0, sizeof(int32_t), st));
     CSBFS_HIP(hipMemsetAsync(e->qcount, 0, sizeof(uint32_t) * P, st));
     CSBFS_HIP(hipMemcpyAsync(e->roots_dev, roots, sizeof(int64_t) * B, hipMemcpyHostToDevice, st));
-    BSeedArgs sa{e->vn, e->view, B * vplane, level, B * n, n};
+    BSeedArgs sa{e->vn, e->fm, e->view, B * vplane, level, B * n, n};
+    // evaluation of each level: top-down, bottom-up, or chosen on the device
+    const int32_t force = (e->flags & CSBFS_FLAG_SPARSE_ONLY)      ? CSBFS_DIR_TOP_DOWN
+                          : (e->flags & CSBFS_FLAG_BOTTOM_UP_ONLY) ? CSBFS_DIR_BOTTOM_UP
+                                                                   : -1;
+    const int32_t dir0 = force == CSBFS_DIR_BOTTOM_UP ? CSBFS_DIR_BOTTOM_UP : CSBFS_DIR_TOP_DOWN;
     const int64_t fill = B * n > B * vplane ? B * n : B * vplane;
     hipLaunchKernelGGL(bseed_fill_kernel, dim3(grid_for(fill, 256, 16384)), dim3(256), 0, st, sa);
     CSBFS_HIP(hipGetLastError());
     hipLaunchKernelGGL(bseed_root_kernel, dim3(1), dim3(64), 0, st, sa, (const int64_t *)e->roots_dev,
-                       (int32_t)B, R, W, (int32_t)P, vplane, e->rootc, e->ctl);
+                       (int32_t)B, R, W, (int32_t)P, vplane, e->rootc, e->ctl, e->dstate, dir0, force, e->dirs);
     CSBFS_HIP(hipGetLastError());
 
     BArgs ea{};
@@ -583,7 +805,18 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
     ea.W = W;
     ea.P = (int32_t)P;
     ea.status = e->status;
+    ea.dir = &e->dstate->cur;
     const unsigned grid = 2048;
+    BPullArgs pa{};
+    pa.vn = e->vn;
+    pa.fm = e->fm;
+    pa.pull_off = g->pull_off;
+    pa.pull_col = g->pull_col;
+    pa.view = e->view;
+    pa.view_words = B * vplane;
+    pa.n = n;
+    pa.B = (int32_t)B;
+    pa.dir = &e->dstate->cur;
 
     WahBatch wb{};
     wb.bits_base = e->f;
@@ -642,10 +875,22 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
         // long rows: 1024 workgroups beat 512, 2048 and 4096 (a sweep, within 2%)
         hipLaunchKernelGGL(bexpand_big_kernel, dim3(1024), dim3(kBThreads), 0, st, ea);
         CSBFS_HIP(hipGetLastError());
+        // the bottom-up evaluation (returns at once on top-down levels); past
+        // the kept counters every root counts as active
+        pa.rootc = j < e->L ? e->rootc + sj * Bm : nullptr;
+        pa.edges = e->edges + sj;
+        pa.fcount = fc;
+        hipLaunchKernelGGL(bpull_kernel, dim3(grid), dim3(kBThreads), 0, st, pa);
+        CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
         BUpdateArgs ua{e->vn, e->f, level, (int32_t)(j + 1), (int32_t)B, n,
-                       e->rootc + sn * Bm, e->ctl + sn, e->qcount, (int32_t)P, fc};
+                       e->rootc + sn * Bm, e->ctl + sn, e->qcount, (int32_t)P, fc,
+                       e->fm, g->deg, e->dstate->sums};
         hipLaunchKernelGGL(bupdate_kernel, dim3(grid_for((words + kBTile - 1) / kBTile, kBThreads / 64, 2048)), dim3(kBThreads), 0, st, ua);
+        CSBFS_HIP(hipGetLastError());
+        // direction of the next level's expansion, from the update's sums
+        hipLaunchKernelGGL(bdir_kernel, dim3(1), dim3(1), 0, st, e->dstate, j + 1 < e->L ? e->dirs + j + 1 : nullptr,
+                           n, kBatchAlpha, kBatchBeta);
         CSBFS_HIP(hipGetLastError());
         if (ev) CSBFS_HIP(hipEventRecord(ev[2], st));
         const int hs = (int)((j + 1) & 1);
@@ -676,7 +921,10 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
     const int64_t want = stats_cap < have ? stats_cap : have;
     std::vector<unsigned long long> rootc, ed, sb, uw;
     std::vector<int64_t> wd;
+    std::vector<int32_t> dr;
     if (want > 0) {
+        dr.resize(want);
+        CSBFS_HIP(hipMemcpyAsync(dr.data(), e->dirs, sizeof(int32_t) * want, hipMemcpyDeviceToHost, st));
         rootc.resize(want * Bm);
         ed.resize(want);
         sb.resize(want * e->Smax);
@@ -700,6 +948,7 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
         csbfs_level_stats &s = stats[lv];
         s = csbfs_level_stats{};
         s.edges = (int64_t)ed[lv];
+        s.direction = dr[lv];
         std::vector<int64_t> send(P, 0), recv(P, 0);
         for (int64_t r = 0; r < B; ++r) {
             const int64_t fr = (int64_t)rootc[lv * Bm + r];

@@ -79,4 +79,10 @@ int sort_rows_desc(uint32_t *col, uint32_t *tmp, const int32_t *row_ptr, const i
 // tile_sum holds scan_tiles(n) entries of scratch.
 int64_t scan_tiles(int64_t n);
 int degree_offsets(const int32_t *deg, int64_t n, int64_t *off, int64_t *tile_sum, hipStream_t st);
+// A batch engine on caller memory: a device block of csbfs_batch_engine_bytes
+// and a pinned two-word host buffer (each may be null: then allocated and
+// owned by the engine); `st` runs its initial zeroing.
+int batch_engine_make(const csbfs_graph *g, int32_t max_roots, int32_t max_levels, uint32_t flags, void *mem,
+                      unsigned long long *host_ctl, hipStream_t st, csbfs_batch_engine **out);
+void batch_engine_release(csbfs_batch_engine *e);
 }

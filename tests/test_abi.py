@@ -76,7 +76,7 @@ def test_host_side_argument_checks(lib):
         assert lib.csbfs_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1, bad
     assert lib.csbfs_server_create(None, ctypes.byref(h)) == -1
     assert lib.csbfs_server_add_graph(None, None, None) == -1
-    assert lib.csbfs_server_submit(None, 0, 0, None, None) == -1
+    assert lib.csbfs_server_submit(None, 0, 0, None, None, None) == -1
     assert lib.csbfs_server_wait(None, 0, None) == -1
     assert lib.csbfs_server_drain(None) == -1
     assert lib.csbfs_server_bytes_held(None) == -1
@@ -122,6 +122,7 @@ def test_server_structs_match_header():
     assert _struct_fields("csbfs_server_config") == [f[0] for f in csbfs.ServerConfig._fields_]
     assert _struct_fields("csbfs_request_info") == [f[0] for f in csbfs.RequestInfo._fields_]
     assert ctypes.sizeof(csbfs.ServerConfig) == 24 and ctypes.sizeof(csbfs.RequestInfo) == 64
+    assert csbfs.lib().csbfs_server_graph_bytes(None, 0) == -1
 
 
 def test_level_stats_layout_matches_header():

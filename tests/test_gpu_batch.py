@@ -89,13 +89,28 @@ def _check_batch(eng, n, p, roots, adj, V, keep=True, max_levels=64, stream_root
     for k, e in enumerate(exp_stats):
         got = r.stats[k]
         for key, val in e.items():
+            if key == "edges" and got["direction"] == 1:
+                # bottom-up: the entries read before every missing root was found
+                assert 0 <= got[key] <= 2 * adj_entries(adj, n), (k, key, got[key])
+                continue
             assert got[key] == val, (k, key, got[key], val)
     return r
 
 
+def adj_entries(adj, n):
+    return sum(adj.degree(v) for v in range(n)) // 2
+
+
+BATCH_MODES = {"auto": 0, "sparse": 8, "bottom_up": 32}
+
+
+@pytest.mark.parametrize("mode", list(BATCH_MODES))
 @pytest.mark.parametrize("scale,p,nroots", [(10, 1, 1), (10, 2, 7), (10, 4, 64), (11, 8, 33),
                                             (12, 4, 64), (12, 1, 64), (13, 2, 20)])
-def test_batch_matches_oracle(scale, p, nroots):
+def test_batch_matches_oracle(scale, p, nroots, mode):
+    """Each evaluation of the batched product (top-down push of root masks,
+    bottom-up pull of frontier masks, or chosen per level) gives every root
+    the levels and streams of its own search."""
     from paper_1208_5542_amd import csbfs
     n = 1 << scale
     src, dst = inputs.rmat_tuples(scale, 16)
@@ -103,9 +118,14 @@ def test_batch_matches_oracle(scale, p, nroots):
     adj = oracle.Adjacency(n, src, dst)
     V = oracle.directory(n, p, src, dst).reshape(-1)
     roots = [int(x) for x in inputs.pick_roots(n, src, dst, nroots, inputs.graph_seed(scale) + 2)]
-    eng = csbfs.BatchEngine(g, max_roots=64, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS)
-    log(f"batch scale={scale} p={p} roots={nroots}")
-    _check_batch(eng, n, p, roots, adj, V, stream_roots=range(min(nroots, 6)))
+    eng = csbfs.BatchEngine(g, max_roots=64, max_levels=64, flags=csbfs.FLAG_KEEP_STREAMS | BATCH_MODES[mode])
+    log(f"batch scale={scale} p={p} roots={nroots} mode={mode}")
+    r = _check_batch(eng, n, p, roots, adj, V, stream_roots=range(min(nroots, 6)))
+    dirs = [s["direction"] for s in r.stats]
+    if mode == "sparse":
+        assert all(d == 0 for d in dirs)
+    if mode == "bottom_up":
+        assert all(d == 1 for d in dirs)
 
 
 def test_batch_repeats_isolated_and_reuse():

@@ -1,7 +1,8 @@
-"""Serving loop: queries over several resident graphs, continuously batched
-into concurrent batched searches under an HBM budget. Every result must be
-identical to the same search alone (the single-root engine, and a server
-that answers one request at a time) and to the oracle's levels."""
+"""Serving loop: queries over several resident graphs, continuously admitted
+into concurrent single-root or batched searches under an HBM budget. Every
+result must be identical to the same search alone (the single-root engine,
+and a server that answers one request at a time) and to the oracle's
+levels; both ways of answering are exercised."""
 import numpy as np
 import pytest
 import torch
@@ -69,7 +70,7 @@ def test_results_identical_alone_and_in_the_mix(pool):
     log("serving: 96 mixed requests on 3 slots")
     outs, infos = _serve(mix, gids, pool, reqs)
     assert all(i["status"] == 0 for i in infos)
-    assert max(i["batch_size"] for i in infos) > 1, "no request was batched with another"
+    assert max(i["batch_size"] for i in infos) > 1, "no request was taken together with another"
     assert all(i["t_submit"] <= i["t_start"] <= i["t_done"] for i in infos)
     # alone: one request at a time on a one-slot server, and the single-root engine
     alone = csbfs.Server(slots=1, max_batch=1, max_levels=64, hbm_budget=1 << 30)
@@ -99,8 +100,9 @@ def test_admission_under_a_small_budget(pool):
     """A budget that holds one engine at a time: requests for different
     graphs are served one engine after the other, never above the budget."""
     from paper_1208_5542_amd import csbfs
-    lib = csbfs.lib()
-    need = max(lib.csbfs_batch_engine_bytes(e["g"].handle, 8, 64, 0) + 4 * 8 * e["n"] for e in pool)
+    probe = csbfs.Server(slots=1, max_batch=8, max_levels=64, hbm_budget=1 << 40)
+    need = max(probe.graph_bytes(probe.add_graph(e["g"])) for e in pool)
+    probe.close()
     server = csbfs.Server(slots=3, max_batch=8, max_levels=64, hbm_budget=need)
     gids = [server.add_graph(e["g"]) for e in pool]
     reqs = _requests(pool, 48, 2)
@@ -118,6 +120,31 @@ def test_admission_under_a_small_budget(pool):
     engines = [csbfs.Engine(e["g"], max_levels=64) for e in pool]
     for (gi, root), o in zip(reqs, outs):
         assert torch.equal(o, engines[gi].bfs(root).level)
+    server.close()
+
+
+def test_both_answer_paths_match(pool):
+    """Bursts of one graph's requests are answered by batched searches and
+    lone requests by single-root searches; both equal the oracle."""
+    from paper_1208_5542_amd import csbfs
+    e = pool[1]
+    server = csbfs.Server(slots=1, max_batch=16, max_levels=64, hbm_budget=1 << 30)
+    gid = server.add_graph(e["g"])
+    burst = [e["roots"][k % len(e["roots"])] for k in range(48)]
+    outs = [torch.full((e["n"],), -7, dtype=torch.int32, device="cuda") for _ in burst]
+    # a burst, queued much faster than one slot answers it
+    ids = [server.submit(gid, root, out) for root, out in zip(burst, outs)]
+    infos = [server.wait(i) for i in ids]
+    # lone requests, each waited for before the next
+    lone = e["roots"][:4]
+    for root in lone:
+        out = torch.full((e["n"],), -7, dtype=torch.int32, device="cuda")
+        infos.append(server.wait(server.submit(gid, root, out)))
+        outs.append(out)
+    assert all(i["status"] == 0 for i in infos)
+    assert any(i["batched"] == 1 for i in infos) and any(i["batched"] == 0 for i in infos)
+    for root, o in zip(burst + lone, outs):
+        assert (o.cpu().numpy() == e["adj"].bfs(root)).all()
     server.close()
 
 
@@ -159,8 +186,9 @@ def test_concurrent_submitters_and_eviction(pool):
     import threading
 
     from paper_1208_5542_amd import csbfs
-    lib = csbfs.lib()
-    need = sorted(lib.csbfs_batch_engine_bytes(e["g"].handle, 16, 64, 0) + 4 * 16 * e["n"] for e in pool)
+    probe = csbfs.Server(slots=1, max_batch=16, max_levels=64, hbm_budget=1 << 40)
+    need = sorted(probe.graph_bytes(probe.add_graph(e["g"])) for e in pool)
+    probe.close()
     budget = need[-1] + need[-2]
     server = csbfs.Server(slots=4, max_batch=16, max_levels=64, hbm_budget=budget)
     gids = [server.add_graph(e["g"]) for e in pool]
