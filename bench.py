@@ -2,8 +2,8 @@
 
 A step is one whole search (every level: expand, update, reduction, sieve,
 WAH compress, decode/merge) from one root. The default workload is an R-MAT
-graph of scale 22 (edgefactor 16, initiator 0.57/0.19/0.19/0.05, ids permuted)
-on a 4 x 4 block grid (p = 4), roots drawn by the seeded root picker; K roots
+graph of scale 26 (edgefactor 16, initiator 0.57/0.19/0.19/0.05, ids permuted)
+on an 8 x 8 block grid (p = 8), roots drawn by the seeded root picker; K roots
 are timed after W warm-up roots. The graph is resident in HBM before timing.
 
 The timed searches run without instrumentation; the same roots are then
@@ -12,12 +12,13 @@ counts, the time split and the roofline.
 
 Prints one JSON line: harmonic-mean GTEPS over the timed roots (TEPS = input
 tuples in the reached component / search time), compression ratios over all
-messages, the expansion step's roofline against HBM bandwidth (algorithmic
-bytes from the level statistics, time from HIP events recorded on the
-library's stream), the batched comparison (64 roots in one batched search
-against the same roots one at a time, R-MAT scale 24), the serving run
-(Poisson queries over a resident pool of six graphs: p50/p99 latency and
-GTEPS) and the CPU oracle timed on a bounded sample.
+messages, each kernel's roofline against HBM bandwidth (algorithmic bytes
+from the level statistics, time from HIP events recorded on the library's
+stream; top-down and bottom-up levels apart), the batched comparison (64
+roots in one batched search against the same roots one at a time, R-MAT
+scale 24), the serving run (Poisson queries over a resident pool of six
+graphs: p50/p99 latency and GTEPS, then a saturating burst) and the CPU
+oracle on the host's cores, timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -63,6 +64,8 @@ def parse():
     ap.add_argument("--serve-qps", type=float, default=2000.0, help="Poisson arrival rate of the serving run")
     ap.add_argument("--serve-requests", type=int, default=4000, help="queries of the serving run")
     ap.add_argument("--serve-slots", type=int, default=4, help="concurrent batched searches")
+    ap.add_argument("--serve-burst", type=int, default=2048,
+                    help="queries of the saturated run (submitted back to back after the Poisson run)")
     ap.add_argument("--json-out", default=None, help="also write a detailed report here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
@@ -112,6 +115,24 @@ def codec_bytes(s: dict, n: int, p: int) -> tuple[int, int]:
     enc = 2 * p * n // 8 + 3 * n // 8 + 8 * s["frontier"] + 8 * words
     dec = 8 * words + p * n // 8
     return enc, dec
+
+
+def batched_bytes(s: dict, n: int, p: int, B: int) -> tuple[int, int]:
+    """Algorithmic bytes of one batched level: its expansion and its update.
+    Top-down expansion: the column ids of every scanned row (4 B) and the
+    visit mask of each target (8 B), plus one pass over the B planes of the
+    p views. Bottom-up expansion: every vertex's visit mask and row offsets
+    (16 B), the column ids read (4 B) and each one's frontier mask (8 B),
+    and the B view planes cleared. Update: visit and discovery masks read
+    (16 B per vertex), frontier masks written (8 B), degrees read (4 B) and
+    the B frontier planes written."""
+    from paper_1208_5542_amd import csbfs
+    if s["direction"] == csbfs.DIR_BOTTOM_UP:
+        exp = 16 * n + 12 * s["edges"] + B * p * n // 8
+    else:
+        exp = 12 * s["edges"] + B * p * n // 8
+    upd = 28 * n + B * n // 8
+    return exp, upd
 
 
 def load_traffic(workload: str):
@@ -251,6 +272,28 @@ def batched_section(args):
         "compression_ratio": round(raw / max(wah, 1), 3),
         "edges_scanned": sum(s["edges"] for s in bstats),
     }
+    # roofline of the batched kernels (instrumented batch), by direction
+    roof = {}
+    for name, want in (("expand_top_down", lambda s: s["direction"] != csbfs.DIR_BOTTOM_UP),
+                       ("expand_bottom_up", lambda s: s["direction"] == csbfs.DIR_BOTTOM_UP)):
+        lv = [s for s in bstats if want(s) and s["ms_expand"] > 0]
+        if lv:
+            by = sum(batched_bytes(s, n, p, B)[0] for s in lv)
+            ms = sum(s["ms_expand"] for s in lv)
+            roof[name] = {"levels": len(lv), "bytes": by, "ms": round(ms, 4),
+                          "achieved": round(by / (ms / 1e3) / 1e9, 1), "unit": "GB/s",
+                          "frac": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    lv = [s for s in bstats if s["ms_update"] > 0]
+    if lv:
+        by = sum(batched_bytes(s, n, p, B)[1] for s in lv)
+        ms = sum(s["ms_update"] for s in lv)
+        roof["update"] = {"levels": len(lv), "bytes": by, "ms": round(ms, 4),
+                          "achieved": round(by / (ms / 1e3) / 1e9, 1), "unit": "GB/s",
+                          "frac": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["roofline"] = roof
+    out["levels_by_direction"] = {
+        "top_down": sum(1 for s in bstats if s["direction"] != csbfs.DIR_BOTTOM_UP),
+        "bottom_up": sum(1 for s in bstats if s["direction"] == csbfs.DIR_BOTTOM_UP)}
     log(f"[bench] batched {out['batched_gteps']} GTEPS vs sequential {out['sequential_gteps']} "
         f"(x{out['speedup']}), levels match: {match}")
     del beng, seng, g
@@ -326,8 +369,13 @@ def serving_section(args):
         ids.append(server.submit(gids[gi], pool[gi]["roots"][ri]))
         meta.append((gi, ri))
     infos = [server.wait(i) for i in ids]
+    # saturated: a burst submitted back to back, so queues build up and the
+    # server batches; its throughput is the pool's capacity
+    bpicks = [(int(rng.integers(len(pool))), int(rng.integers(128))) for _ in range(args.serve_burst)]
+    bids = [server.submit(gids[gi], pool[gi]["roots"][ri]) for gi, ri in bpicks]
+    binfos = [server.wait(i) for i in bids]
     server.close()
-    bad = sum(1 for i in infos if i["status"] != 0)
+    bad = sum(1 for i in infos + binfos if i["status"] != 0)
     lat = np.array([i["t_done"] - i["t_submit"] for i in infos]) * 1e3
     span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
     m_tot = sum(pool[gi]["m"][ri] for gi, ri in meta)
@@ -351,7 +399,27 @@ def serving_section(args):
                             "(sum of tuples / sum of search times)",
         "mean_batch": round(float(np.mean([i["batch_size"] for i in infos])), 2),
         "batched_fraction": round(float(np.mean([i["batched"] for i in infos])), 3),
+        "note": "at the offered rate the served rate is bounded by the arrivals (tuples of the "
+                "requests per second); the saturated run gives the capacity",
     }
+    if binfos:
+        bspan = max(i["t_done"] for i in binfos) - min(i["t_submit"] for i in binfos)
+        bm = sum(pool[gi]["m"][ri] for gi, ri in bpicks)
+        bt = sum(pool[gi]["t_single"][ri] for gi, ri in bpicks)
+        blat = np.array([i["t_done"] - i["t_submit"] for i in binfos]) * 1e3
+        out["saturated"] = {
+            "requests": len(binfos), "achieved_qps": round(len(binfos) / bspan, 1),
+            "gteps": round(bm / bspan / 1e9, 4),
+            "single_root_gteps_same_requests": round(bm / bt / 1e9, 4),
+            "mean_batch": round(float(np.mean([i["batch_size"] for i in binfos])), 2),
+            "batched_fraction": round(float(np.mean([i["batched"] for i in binfos])), 3),
+            "latency_ms": {"p50": round(float(np.percentile(blat, 50)), 3),
+                           "p99": round(float(np.percentile(blat, 99)), 3)},
+        }
+        log(f"[bench] serving saturated: {out['saturated']['achieved_qps']} qps, "
+            f"{out['saturated']['gteps']} GTEPS (single-root alone "
+            f"{out['saturated']['single_root_gteps_same_requests']}), mean batch "
+            f"{out['saturated']['mean_batch']}, batched {out['saturated']['batched_fraction']}")
     log(f"[bench] serving: {out['achieved_qps']} qps, p50 {out['latency_ms']['p50']} ms, "
         f"p99 {out['latency_ms']['p99']} ms, {out['gteps']} GTEPS (single-root alone "
         f"{out['single_root_gteps_same_requests']}), mean batch {out['mean_batch']}, "

@@ -6,8 +6,9 @@
  * Parallel Breadth First Search on Distributed Memory Systems" (2012):
  * Algorithm 3 (Sec. V.B) over p virtual processors held as buffers on one
  * GPU. Processor P_i owns the contiguous vertex range
- * R_i = [i*n/p, (i+1)*n/p). Every level runs top-down expansion over the
- * sub-blocks A_{i,j} (Eq. sub-block), the mask and update of the visited
+ * R_i = [i*n/p, (i+1)*n/p). Every level runs the expansion over the
+ * sub-blocks A_{i,j} (Eq. sub-block; a top-down push, or a bottom-up pull
+ * over the same entries, chosen per level), the mask and update of the visited
  * vector, the frontier-size reduction, the sieve of every outgoing message
  * with the cross directory (Eq. dir-vec, Eq. cross-dir), WAH compression
  * (Sec. IV, Table 3), and decompression into the receivers' frontier views.

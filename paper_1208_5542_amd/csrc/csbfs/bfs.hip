@@ -82,6 +82,33 @@ struct BlockMarks {
     __device__ __forceinline__ bool word_marked(int64_t q) const { return m[q >> kMarkShift] != 0; }
 };
 
+// Workgroups of a launch are dealt to the 8 XCDs round-robin (workgroup b
+// runs on XCD b % 8, as a probe of the XCC id register showed), and each XCD
+// has its own L2. When p divides 8, a kernel whose workgroups on XCD x all
+// work for processor x % p keeps that processor's data (its n-bit view, its
+// piece of the frontier) in the L2 of 8 / p XCDs instead of spreading every
+// processor's data over all eight.
+constexpr int kXcds = 8;
+inline bool xcd_split(int64_t P, int64_t grid) { return P >= 1 && P <= kXcds && kXcds % P == 0 && grid % kXcds == 0; }
+
+// Stream of encoder workgroup b of a one-dimensional grid of S * nseg: with
+// the split, the p streams i -> 0..p-1 of sender i run on the XCDs x with
+// x % p == i, taking turns, so the p workgroups that stage one segment of
+// f_i (one per receiver) find its words in one L2; without it the streams
+// lie one after another. `first` marks one workgroup per stream.
+__device__ __forceinline__ void enc_stream_of(int64_t b, int32_t P, int64_t nseg, bool split, int64_t &s,
+                                              bool &first) {
+    if (!split) {
+        s = b / nseg;
+        first = b - s * nseg == 0;
+        return;
+    }
+    const int x = (int)(b % kXcds);
+    const int64_t kk = (b / kXcds) * (kXcds / P) + x / P;  // turn among sender x % p's workgroups
+    s = (int64_t)(x % P) * P + kk % P;
+    first = kk < P;
+}
+
 struct ExpandArgs {
     const uint64_t *view;
     uint64_t *view_clear;      // the same views: the push zeroes each non-zero word it takes
@@ -361,6 +388,8 @@ struct PullArgs {
     int64_t W;
     int32_t P;
     int32_t tile_words;  // bitmap words per wave tile (<= 64)
+    int32_t xcd;         // tiles of processor x % p on XCD x (p divides 8, the grid is a
+                         // multiple of 8 and a processor's words a multiple of the tile)
     int32_t *status;
     const int32_t *dir;
     unsigned long long *edges;   // bottom-up: entries read
@@ -391,10 +420,22 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t tw_n = a.tile_words;  // <= kPullTileBU in bottom-up
-    const int64_t ntiles = (a.words + tw_n - 1) / tw_n;
+    // tiles tbase + u for u = u0, u0 + ustep, ... < uend: all tiles, or those of
+    // processor x % p (x = this workgroup's XCD) spread over its 8 / p XCDs, so
+    // that each XCD reads one processor's view (P_i's n-bit map)
+    int64_t tbase = 0, u0 = wave, ustep = nwaves, uend = (a.words + tw_n - 1) / tw_n;
+    if (a.xcd) {
+        const int x = (int)(blockIdx.x % kXcds), c = kXcds / a.P;
+        const int64_t wpw = blockDim.x >> 6;
+        uend = a.W / tw_n;
+        tbase = (int64_t)(x % a.P) * uend;
+        u0 = ((int64_t)(blockIdx.x / kXcds) * c + x / a.P) * wpw + wid;
+        ustep = (int64_t)(gridDim.x / kXcds) * c * wpw;
+    }
     unsigned long long read = 0, examined = 0;
     if (kBottomUp && lane < kPullTileBU) found_bits[wid][lane] = 0;
-    for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
+    for (int64_t u = u0; u < uend; u += ustep) {
+        const int64_t tile = tbase + u;
         const int64_t wq = tile * tw_n + lane;
         uint64_t t = 0;
         if (lane < tw_n && wq < a.words)
@@ -707,11 +748,14 @@ struct FrontierHook {
 // segment). Returns at once once the search has ended.
 template <int kGpt>
 __global__ __launch_bounds__(kEncThreads) void frontier_encode_kernel(WahBatch b, FrontierHook h,
-                                                                      const DirState *st) {
+                                                                      const DirState *st, int32_t split) {
     const int32_t d = st->cur;  // the direction f^(k-1) was expanded in
     if (d == kDirIdle) return;
     h.clear_views = d != kDirTD;  // the sparse push zeroes the view words it reads
-    encode_segment<kGpt>(b, h);
+    int64_t s;
+    bool first;
+    enc_stream_of(blockIdx.x, b.P, b.nseg, split != 0, s, first);
+    encode_segment<kGpt>(b, h, s, first);
 }
 
 struct ReduceArgs {
@@ -1120,6 +1164,9 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
     const unsigned exp_grid = 512, big_grid = 256;
     const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
     const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 2048);
+    pa.xcd = xcd_split(P, pull_grid) && W % kPullTileDense == 0;
+    pb.xcd = xcd_split(P, exp_grid) && W % kPullTileBU == 0;
+    const int32_t bu_xcd = xcd_split(P, bu_grid) && W % kPullTileBU == 0;
     DirArgs da{};
     da.st = w.dstate;
     da.n = n;
@@ -1142,7 +1189,8 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
     wb.chunk_starts = 1;  // the decode reads the chunk starts the encode records
     wb.dst_base = w.view;
     wb.status = w.status;
-    const dim3 enc_grid((unsigned)y.nseg, (unsigned)S),
+    const int32_t enc_split = xcd_split(P, S * y.nseg);
+    const dim3 enc_grid((unsigned)(S * y.nseg)),
         dec_grid((unsigned)std::min<int64_t>(y.nchunk, kDecGridChunks), (unsigned)S);
 
     // Iteration j: for j >= 1 the update that forms f^j together with the
@@ -1170,10 +1218,10 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
                             marks_of(j), marks_of(j + 1), W, y.seg_words, (int32_t)P, (int32_t)j, 1};
             if (y.enc_gpt == 2)
                 hipLaunchKernelGGL(frontier_encode_kernel<2>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
-                                   (const DirState *)w.dstate);
+                                   (const DirState *)w.dstate, enc_split);
             else
                 hipLaunchKernelGGL(frontier_encode_kernel<4>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
-                                   (const DirState *)w.dstate);
+                                   (const DirState *)w.dstate, enc_split);
             CSBFS_HIP(hipGetLastError());
             if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));
             // a6: the stream slots are the receive buffers; a7: decode into the
@@ -1214,7 +1262,9 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
             pb.edges = w.lc.edges + sj;
             pb.pulled = w.lc.pulled + sj;
             if (bu_only) {
-                hipLaunchKernelGGL(pull_kernel<true>, dim3(bu_grid), dim3(kPullThreads), 0, st, pb);
+                PullArgs pbu = pb;
+                pbu.xcd = bu_xcd;
+                hipLaunchKernelGGL(pull_kernel<true>, dim3(bu_grid), dim3(kPullThreads), 0, st, pbu);
                 CSBFS_HIP(hipGetLastError());
                 if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
             } else {

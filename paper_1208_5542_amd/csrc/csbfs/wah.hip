@@ -10,7 +10,7 @@ namespace {
 
 __global__ __launch_bounds__(kEncThreads) void wah_encode_kernel(WahBatch b) {
     PlainWords h;
-    encode_segment<kEncGpt>(b, h);
+    encode_segment<kEncGpt>(b, h, blockIdx.y, blockIdx.x == 0);
 }
 
 __global__ __launch_bounds__(kDecThreads) void wah_dec_count(WahBatch b) { dec_count_body(b); }

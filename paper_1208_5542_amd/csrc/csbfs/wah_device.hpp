@@ -304,9 +304,11 @@ __device__ uint64_t lb_prefix(const WahBatch &b, unsigned long long *look, int64
 //
 // The hook stages the words (Hook::load), may do other work with waves 1..
 // while wave 0 looks back (Hook::side), and finishes that work with thread 0
-// (Hook::finish) once the workgroup's sums are in.
+// (Hook::finish) once the workgroup's sums are in. The workgroup encodes a
+// segment of stream s; `first` marks one workgroup per stream (it reports
+// the empty stream of a skipped plane).
 template <int kGpt, class Hook>
-__device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook) {
+__device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, int64_t s, bool first) {
     constexpr int kSeg = kEncThreads * kGpt;  // groups per segment
     constexpr int kLds = enc_lds_words(kSeg);
     __shared__ uint64_t sw[kLds];
@@ -316,9 +318,8 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook) {
     __shared__ int sh_last_cls;
     __shared__ uint64_t sh_prefix;
     __shared__ bool sh_reset;
-    const int64_t s = blockIdx.y;
     if (plane_skipped(b, s)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) b.n_words[s] = 0;
+        if (first && threadIdx.x == 0) b.n_words[s] = 0;
         return;
     }
     // segments in the order the workgroups start, so every awaited one runs
