@@ -248,14 +248,16 @@ int csbfs_layout_query(int64_t n, int64_t n_tuples, int32_t p, const csbfs_searc
 /*
  * Allocate (hipMalloc) a search workspace of Algorithm 3 for graph g, the
  * one csbfs_bfs_ws takes for a config of these flags and max_levels:
- * visited vector pi (two copies, one per level parity; f_i and t_i are
- * formed inside the encoder and never stored), the p frontier views (p * n
- * bits), the WAH stream arena (p * p streams of floor((n/p)/63) + 1 words,
- * times max_levels with CSBFS_FLAG_KEEP_STREAMS), the expansion work queue
- * and the per-level counters for up to max_levels levels (1 <= max_levels
- * <= 65536); plus a pinned two-word mailbox and, with CSBFS_FLAG_TIMING,
- * four events per level. The graph must outlive the engine. The encoder's
- * segment size is chosen from n/p and p. Errors: EINVAL, EHIP.
+ * visited vector pi, the bitmaps of the vertices discovered by the last two
+ * expansions (t_i, which becomes f_i; one per level parity), a mark per
+ * 4096 vertices per level parity telling which parts of them may be
+ * non-zero, the p frontier views (p * n bits), the WAH stream arena (p * p
+ * streams of floor((n/p)/63) + 1 words, times max_levels with
+ * CSBFS_FLAG_KEEP_STREAMS), the expansion work queue and the per-level
+ * counters for up to max_levels levels (1 <= max_levels <= 65536); plus a
+ * pinned two-word mailbox and, with CSBFS_FLAG_TIMING, five events per
+ * level. The graph must outlive the engine. The encoder's segment size is
+ * chosen from n/p and p. Errors: EINVAL, EHIP.
  */
 int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags,
                         csbfs_engine **out);

@@ -48,7 +48,8 @@ namespace {
 
 constexpr int kExpThreads = 512;
 constexpr int kPullThreads = 512;
-constexpr int kPullRounds = 16;  // per-lane steps (kUnroll entries each) before the wave helps
+constexpr int kPullRounds = 16;  // per-lane steps (kPullUnroll entries each) before the wave helps
+constexpr int kPullUnroll = 2;   // entries per lane step of the pull
 constexpr int kEvPerLevel = 5;  // before/after the update + encode, after the decode, after the
                                 // main expansion kernel, after the long rows
 constexpr int kPullTileDense = 64;  // bitmap words per wave tile of the dense pull
@@ -409,7 +410,7 @@ struct PullArgs {
 //       stays unvisited. The found ones are gathered per bitmap word in LDS
 //       and set in N by the wave that owns the word.
 // A wavefront takes tile_words bitmap words at a time and ranks their
-// candidates, 64 at a time (lane = v). Each lane reads kUnroll entries per
+// candidates, 64 at a time (lane = v). Each lane reads kPullUnroll entries per
 // step; lanes still searching after kPullRounds steps are finished by the
 // whole wave, 64 entries per step.
 template <bool kBottomUp>
@@ -465,20 +466,20 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
             bool busy = mine && e < re;
             for (int round = 0; round < kPullRounds; ++round) {
                 if (busy) {
-                    // every lane reads kUnroll entries, positions past the row end
+                    // every lane reads kPullUnroll entries, positions past the row end
                     // clamped to its last entry and masked out of the hits: the
                     // loads need no per-entry branch
-                    const int32_t nk = re - e < kUnroll ? (int32_t)(re - e) : kUnroll;
+                    const int32_t nk = re - e < kPullUnroll ? (int32_t)(re - e) : kPullUnroll;
                     const uint32_t *cp = a.pull_col + e;
-                    uint32_t c[kUnroll];
-                    uint64_t x[kUnroll];
+                    uint32_t c[kPullUnroll];
+                    uint64_t x[kPullUnroll];
 #pragma unroll
-                    for (int k = 0; k < kUnroll; ++k) c[k] = cp[k < nk ? k : nk - 1];
+                    for (int k = 0; k < kPullUnroll; ++k) c[k] = cp[k < nk ? k : nk - 1];
 #pragma unroll
-                    for (int k = 0; k < kUnroll; ++k) x[k] = vw[c[k] >> 6];
+                    for (int k = 0; k < kPullUnroll; ++k) x[k] = vw[c[k] >> 6];
                     uint32_t hm = 0;
 #pragma unroll
-                    for (int k = 0; k < kUnroll; ++k) hm |= (uint32_t)((x[k] >> (c[k] & 63)) & 1) << k;
+                    for (int k = 0; k < kPullUnroll; ++k) hm |= (uint32_t)((x[k] >> (c[k] & 63)) & 1) << k;
                     hm &= (1u << nk) - 1u;
                     if (hm) {
                         const int hit = __builtin_ctz(hm);
