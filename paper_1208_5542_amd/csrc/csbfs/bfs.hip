@@ -384,6 +384,9 @@ struct PullArgs {
     const int64_t *pull_off;   // merged rows (global ids, decreasing) of every vertex
     const uint32_t *pull_col;
     int32_t *parent;
+    int32_t *level;            // the found vertices' level (next_level); their
+    unsigned long long *mf;    // adjacency entries (merged row lengths) are summed here
+    int32_t next_level;
     int64_t words;  // n / 64
     int64_t R;
     int64_t W;
@@ -409,6 +412,9 @@ struct PullArgs {
 //       adjacency entry (~pi & live); one that finds no frontier neighbour
 //       stays unvisited. The found ones are gathered per bitmap word in LDS
 //       and set in N by the wave that owns the word.
+// Either way the lane that finds v's parent also writes v's level and adds
+// v's adjacency entries (its merged row's length) to the level's sum, so
+// the update of f^(k+1) does not visit v again.
 // A wavefront takes tile_words bitmap words at a time and ranks their
 // candidates, 64 at a time (lane = v). Each lane reads kPullUnroll entries per
 // step; lanes still searching after kPullRounds steps are finished by the
@@ -433,7 +439,7 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
         u0 = ((int64_t)(blockIdx.x / kXcds) * c + x / a.P) * wpw + wid;
         ustep = (int64_t)(gridDim.x / kXcds) * c * wpw;
     }
-    unsigned long long read = 0, examined = 0;
+    unsigned long long read = 0, examined = 0, mf = 0;
     if (kBottomUp && lane < kPullTileBU) found_bits[wid][lane] = 0;
     for (int64_t u = u0; u < uend; u += ustep) {
         const int64_t tile = tbase + u;
@@ -461,6 +467,7 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
                 e = a.pull_off[v];
                 re = a.pull_off[v + 1];
             }
+            const int64_t dv = re - e;  // v's adjacency entries: its merged row is all of them
             const int64_t i = v / a.R;
             const uint64_t *vw = a.view + i * a.P * a.W;  // P_i's views as one n-bit map
             bool busy = mine && e < re;
@@ -525,6 +532,8 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
             if (mine) {
                 if (found >= 0) {
                     a.parent[v] = found;
+                    a.level[v] = a.next_level;
+                    mf += (unsigned long long)dv;
                     if (kBottomUp) atomicOr(&found_bits[wid][L], 1ull << bitpos);
                 } else if (!kBottomUp) {
                     *a.status = 3;  // a vertex seen in this level has a frontier neighbour
@@ -545,10 +554,13 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
             wave_lds_sync();
         }
     }
+    for (int d = 32; d > 0; d >>= 1) mf += (unsigned long long)shfl64((int64_t)mf, lane ^ d);
     if (kBottomUp) {
         for (int d = 32; d > 0; d >>= 1) read += (unsigned long long)shfl64((int64_t)read, lane ^ d);
         block_add<kPullThreads / 64>(read, a.edges, examined, a.pulled);
+        __syncthreads();  // block_add's LDS is used again below
     }
+    block_add<kPullThreads / 64>(mf, a.mf);
 }
 
 template <bool kBottomUp>
@@ -642,9 +654,9 @@ __device__ __forceinline__ unsigned long long *update_sums() {
 // hold bits of f^(k-1) that the last expansion did not zero, and, with the
 // other p - 1 workgroups of sender i's segment, takes the segment's 8-word
 // steps round-robin: pi |= f, the other copy N_old (the previous frontier)
-// cleared for the next expansion, then level and adjacency-entry count of
-// every new vertex (lane = vertex; all masked loads of a step in flight
-// before any is summed). Each word is taken by one lane, and no workgroup
+// cleared for the next expansion, then, if f came from a push (a pull did it
+// already), level and adjacency-entry count of every new vertex (lane =
+// vertex; all masked loads of a step in flight before any is summed). Each word is taken by one lane, and no workgroup
 // of this launch reads pi or N_old, so the plain read-modify-writes need no
 // atomics.
 struct FrontierHook {
@@ -662,6 +674,7 @@ struct FrontierHook {
     int32_t P;
     int32_t lvl;  // k
     int32_t clear_views;  // the expansion of f^(k-1) left its view words in place
+    int32_t write_levels;  // the expansion of f^(k-1) was a push: levels and entries of f^k here
 
     __device__ __forceinline__ uint64_t load(const WahBatch &, int64_t, int64_t i, int64_t w) const {
         return N_cur[i * W + w];
@@ -714,7 +727,7 @@ struct FrontierHook {
                 if (mark_old.word_marked(base + qk) && N_old[base + qk]) N_old[base + qk] = 0;
                 cnt += (unsigned long long)__popcll(tk);
             }
-            if (!__ballot(tk != 0)) continue;
+            if (!write_levels || !__ballot(tk != 0)) continue;
             int32_t d[kUpdWords];
 #pragma unroll
             for (int k = 0; k < kUpdWords; ++k) {
@@ -753,6 +766,7 @@ __global__ __launch_bounds__(kEncThreads) void frontier_encode_kernel(WahBatch b
     const int32_t d = st->cur;  // the direction f^(k-1) was expanded in
     if (d == kDirIdle) return;
     h.clear_views = d != kDirTD;  // the sparse push zeroes the view words it reads
+    h.write_levels = d == kDirTD;  // a pull wrote the levels of the vertices it found
     int64_t s;
     bool first;
     enc_stream_of(blockIdx.x, b.P, b.nseg, split != 0, s, first);
@@ -769,6 +783,7 @@ struct ReduceArgs {
     int32_t level;                   // k
     uint32_t *marks_clear;           // [nmarks]: the marks of f^(k-1), cleared for the next expansion
     int64_t nmarks;
+    unsigned long long *exp_mf;      // entries of the vertices a pull found, cleared here
     DirArgs dir;
 };
 
@@ -790,6 +805,8 @@ __global__ __launch_bounds__(kDecThreads) void search_decode_kernel(WahBatch b, 
         if (threadIdx.x < r.P) r.ctrs[threadIdx.x] = 0;
         for (int64_t k = threadIdx.x; k < r.nmarks; k += blockDim.x) r.marks_clear[k] = 0;
         if (threadIdx.x == 0) {
+            mf += *r.exp_mf;  // f^k came from a pull: its entries were summed there
+            *r.exp_mf = 0;
             r.total[0] = nf;
             r.total[1] = mf;
             // one 64-bit word (level tag, |f^k|) so the host sees both or neither
@@ -924,6 +941,7 @@ struct SearchState {
     int32_t *status;
     uint32_t *ctrs;  // [P]: chunk-queue items pushed
     uint32_t *marks[2];  // block marks by level parity: marks[k & 1] for f^k
+    unsigned long long *exp_mf;  // adjacency entries of the vertices a pull found (one level)
 };
 
 constexpr uint32_t kSearchFlags = CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE | CSBFS_FLAG_SPARSE_ONLY |
@@ -986,7 +1004,7 @@ int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *
     // everything a search starts from zero, in one block the seed clears:
     // per-level counters, then the status flag and the queue counts
     const int64_t slots = y.L + 1;
-    y.counters_bytes = 8 * slots * (2 + y.P + 1 + 1 + y.S + y.P) + 8 * slots * y.S + 4 * slots + 4 * (2 + y.P);
+    y.counters_bytes = 8 + 8 * slots * (2 + y.P + 1 + 1 + y.S + y.P) + 8 * slots * y.S + 4 * slots + 4 * (2 + y.P);
     y.counters_bytes = (y.counters_bytes + 3) / 4 * 4;
     y.counters = take(y.counters_bytes);
     y.total = o;
@@ -1013,6 +1031,7 @@ SearchState bind_workspace(const SearchLayout &y, void *ws) {
     w.counters_mem = b + y.counters;
     const int64_t slots = y.L + 1, P = y.P, S = y.S;
     unsigned long long *c = (unsigned long long *)w.counters_mem;
+    w.exp_mf = c++;
     w.lc.ctl = c;
     c += slots * 2;
     w.lc.rank = c;
@@ -1149,6 +1168,8 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
     pa.view = w.view;
     pa.pull_off = g->pull_off;
     pa.pull_col = g->pull_col;
+    pa.level = level;
+    pa.mf = w.exp_mf;
     pa.parent = parent;
     pa.words = words;
     pa.R = R;
@@ -1216,7 +1237,7 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
             wb.stat_sieved_bits = w.lc.sbits + sj * S;
             wb.stat_unsieved_words = w.lc.uwords + sj * P;
             FrontierHook fh{w.nb[j & 1], w.nb[(j + 1) & 1], w.pi, w.view, level, g->deg, w.part,
-                            marks_of(j), marks_of(j + 1), W, y.seg_words, (int32_t)P, (int32_t)j, 1};
+                            marks_of(j), marks_of(j + 1), W, y.seg_words, (int32_t)P, (int32_t)j, 1, 1};
             if (y.enc_gpt == 2)
                 hipLaunchKernelGGL(frontier_encode_kernel<2>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
                                    (const DirState *)w.dstate, enc_split);
@@ -1229,7 +1250,7 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
             // views; a3: reduction of |f^j|, direction of its expansion
             da.rec = w.lc.dir + sj;
             ReduceArgs ra{w.part, S * y.nseg, w.lc.ctl + 2 * sj, mb.dev ? mb.dev + (j & 1) : nullptr, w.ctrs,
-                          (int32_t)P, (int32_t)j, w.marks[(j + 1) & 1], y.nmarks, da};
+                          (int32_t)P, (int32_t)j, w.marks[(j + 1) & 1], y.nmarks, w.exp_mf, da};
             hipLaunchKernelGGL(search_decode_kernel, dec_grid, dim3(kDecThreads), 0, st, wb, ra);
             CSBFS_HIP(hipGetLastError());
         } else if (ev) {
@@ -1239,6 +1260,8 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
         ea.N = w.nb[(j + 1) & 1];
         pa.N = w.nb[(j + 1) & 1];
         pb.N = w.nb[(j + 1) & 1];
+        pa.next_level = (int32_t)(j + 1);
+        pb.next_level = (int32_t)(j + 1);
         ea.marks_next = marks_of(j + 1);
         ea.marks_view = marks_of(j);
         pa.marks_next = marks_of(j + 1);
