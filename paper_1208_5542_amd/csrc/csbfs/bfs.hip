@@ -50,6 +50,7 @@ constexpr int kExpThreads = 512;
 constexpr int kPullThreads = 512;
 constexpr int kPullRounds = 16;  // per-lane steps (kPullUnroll entries each) before the wave helps
 constexpr int kPullUnroll = 2;   // entries per lane step of the pull
+constexpr int kPullWindow = 4;   // row entries a lane loads at once (a multiple of kPullUnroll; 4 beat 8 and 16)
 constexpr int kEvPerLevel = 5;  // before/after the update + encode, after the decode, after the
                                 // main expansion kernel, after the long rows
 constexpr int kPullTileDense = 64;  // bitmap words per wave tile of the dense pull
@@ -471,32 +472,43 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
             const int64_t i = v / a.R;
             const uint64_t *vw = a.view + i * a.P * a.W;  // P_i's views as one n-bit map
             bool busy = mine && e < re;
-            for (int round = 0; round < kPullRounds; ++round) {
+            // kPullWindow entries of the row are loaded at once (positions past
+            // the row end clamped to its last entry) and tested kPullUnroll at a
+            // time, hits past the end masked out: the loads need no per-entry
+            // branch, and a row's cache line is fetched once per window instead
+            // of once per step
+            for (int wr = 0; wr < kPullRounds * kPullUnroll / kPullWindow; ++wr) {
+                uint32_t win[kPullWindow];
                 if (busy) {
-                    // every lane reads kPullUnroll entries, positions past the row end
-                    // clamped to its last entry and masked out of the hits: the
-                    // loads need no per-entry branch
-                    const int32_t nk = re - e < kPullUnroll ? (int32_t)(re - e) : kPullUnroll;
+                    const int32_t wn = re - e < kPullWindow ? (int32_t)(re - e) : kPullWindow;
                     const uint32_t *cp = a.pull_col + e;
-                    uint32_t c[kPullUnroll];
-                    uint64_t x[kPullUnroll];
 #pragma unroll
-                    for (int k = 0; k < kPullUnroll; ++k) c[k] = cp[k < nk ? k : nk - 1];
+                    for (int k = 0; k < kPullWindow; ++k) win[k] = cp[k < wn ? k : wn - 1];
+                }
 #pragma unroll
-                    for (int k = 0; k < kPullUnroll; ++k) x[k] = vw[c[k] >> 6];
-                    uint32_t hm = 0;
+                for (int h = 0; h < kPullWindow / kPullUnroll; ++h) {
+                    if (busy) {
+                        const int32_t nk = re - e < kPullUnroll ? (int32_t)(re - e) : kPullUnroll;
+                        uint32_t c[kPullUnroll];
+                        uint64_t x[kPullUnroll];
 #pragma unroll
-                    for (int k = 0; k < kPullUnroll; ++k) hm |= (uint32_t)((x[k] >> (c[k] & 63)) & 1) << k;
-                    hm &= (1u << nk) - 1u;
-                    if (hm) {
-                        const int hit = __builtin_ctz(hm);
-                        found = (int32_t)c[hit];
-                        busy = false;
-                        read += (unsigned long long)(hit + 1);
-                    } else {
-                        read += (unsigned long long)nk;
-                        e += nk;
-                        if (e >= re) busy = false;  // row exhausted: no frontier neighbour
+                        for (int k = 0; k < kPullUnroll; ++k) c[k] = win[h * kPullUnroll + k];
+#pragma unroll
+                        for (int k = 0; k < kPullUnroll; ++k) x[k] = vw[c[k] >> 6];
+                        uint32_t hm = 0;
+#pragma unroll
+                        for (int k = 0; k < kPullUnroll; ++k) hm |= (uint32_t)((x[k] >> (c[k] & 63)) & 1) << k;
+                        hm &= (1u << nk) - 1u;
+                        if (hm) {
+                            const int hit = __builtin_ctz(hm);
+                            found = (int32_t)c[hit];
+                            busy = false;
+                            read += (unsigned long long)(hit + 1);
+                        } else {
+                            read += (unsigned long long)nk;
+                            e += nk;
+                            if (e >= re) busy = false;  // row exhausted: no frontier neighbour
+                        }
                     }
                 }
                 if (!__ballot(busy)) break;
