@@ -295,28 +295,48 @@ __device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int6
 // sources are spread evenly over the lanes, kUnroll edges per lane per step.
 template <bool kDense>
 __device__ __forceinline__ void expand_body(const ExpandArgs &a) {
+    const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t ntiles = (a.rank_words + a.tile_words - 1) / a.tile_words;
     unsigned long long edges = 0;
-    // kTilesAhead tiles' words are loaded before any is looked at: most
-    // tiles of a small frontier are empty, and their loads then overlap
+    // The wave's tiles are gt = wave + i * nwaves (tile gt % ntiles of
+    // processor gt / ntiles; both below 2^31). Lane i reads the block mark of
+    // the wave's i-th tile of a batch of 64, so only marked tiles are read:
+    // most tiles of a small frontier are empty. kTilesAhead marked tiles'
+    // words are loaded before any is looked at, so their loads overlap.
     const int64_t total = ntiles * a.P;
-    for (int64_t gt0 = wave; gt0 < total; gt0 += nwaves * kTilesAhead) {
-        uint64_t bits[kTilesAhead];
-#pragma unroll
-        for (int k = 0; k < kTilesAhead; ++k) {
-            const int64_t gt = gt0 + k * nwaves;
-            const int32_t r = (int32_t)(gt / ntiles);
-            bits[k] = gt < total ? tile_word(a, r, gt - (int64_t)r * ntiles) : 0;
+    for (int64_t g0 = wave; g0 < total; g0 += nwaves * 64) {
+        const int64_t mine = g0 + (int64_t)lane * nwaves;
+        bool marked = false;
+        if (mine < total) {
+            const uint32_t r = (uint32_t)mine / (uint32_t)ntiles;
+            const int64_t t = mine - (int64_t)r * ntiles;
+            marked = a.marks_view.m[(t * a.tile_words) >> kMarkShift] != 0;
         }
+        uint64_t todo = __ballot(marked);
+        while (todo) {
+            int32_t rs[kTilesAhead];
+            int64_t ts[kTilesAhead];
+            uint64_t bits[kTilesAhead];
 #pragma unroll
-        for (int k = 0; k < kTilesAhead; ++k) {
-            const int64_t gt = gt0 + k * nwaves;
-            if (gt < total && __ballot(bits[k] != 0)) {
-                const int32_t r = (int32_t)(gt / ntiles);
-                expand_tile<kDense>(a, r, gt - (int64_t)r * ntiles, bits[k], edges);
+            for (int k = 0; k < kTilesAhead; ++k) {
+                rs[k] = -1;
+                ts[k] = 0;
+                bits[k] = 0;
+                if (todo) {
+                    const int idx = __ffsll((unsigned long long)todo) - 1;
+                    todo &= todo - 1;
+                    const int64_t gt = g0 + (int64_t)idx * nwaves;
+                    const uint32_t r = (uint32_t)gt / (uint32_t)ntiles;
+                    rs[k] = (int32_t)r;
+                    ts[k] = gt - (int64_t)r * ntiles;
+                    bits[k] = tile_word(a, (int32_t)r, ts[k]);
+                }
             }
+#pragma unroll
+            for (int k = 0; k < kTilesAhead; ++k)
+                if (rs[k] >= 0 && __ballot(bits[k] != 0)) expand_tile<kDense>(a, rs[k], ts[k], bits[k], edges);
         }
     }
     // `total` is wave-uniform, so every lane holds the wave's edge count
