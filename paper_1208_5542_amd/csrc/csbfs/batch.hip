@@ -726,8 +726,8 @@ int batch_engine_make(const csbfs_graph *g, int32_t max_roots, int32_t max_level
         if (herr == hipSuccess) herr = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (herr == hipSuccess && (flags & CSBFS_FLAG_TIMING)) {
         e->events.assign((size_t)max_levels * kBEvPerLevel, nullptr);
-        for (auto &ev : e->events)
-            if (herr == hipSuccess) herr = hipEventCreate(&ev);
+        for (auto &ev : e->events)  // timestamps only: no system-scope fence at each record
+            if (herr == hipSuccess) herr = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);
     }
     if (herr != hipSuccess) {
         bengine_release(e.release());

@@ -404,6 +404,7 @@ struct PullArgs {
     const uint64_t *view;
     const int64_t *pull_off;   // merged rows (global ids, decreasing) of every vertex
     const uint32_t *pull_col;
+    const uint32_t *head;      // [2n]: the first two ids of each merged row
     int32_t *parent;
     int32_t *level;            // the found vertices' level (next_level); their
     unsigned long long *mf;    // adjacency entries (merged row lengths) are summed here
@@ -480,6 +481,7 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
             const int rr = r - __shfl(excl_b, L, 64);
             const bool mine = r < tot_b;
             int64_t v = 0, e = 0, re = 0;
+            uint2 hd = make_uint2(0u, 0u);
             int bitpos = 0;
             int32_t found = -1;
             if (mine) {
@@ -487,11 +489,31 @@ __device__ __forceinline__ void pull_body(const PullArgs &a) {
                 v = ((tile * tw_n + L) << 6) + bitpos;
                 e = a.pull_off[v];
                 re = a.pull_off[v + 1];
+                hd = *reinterpret_cast<const uint2 *>(a.head + 2 * v);
             }
             const int64_t dv = re - e;  // v's adjacency entries: its merged row is all of them
             const int64_t i = v / a.R;
             const uint64_t *vw = a.view + i * a.P * a.W;  // P_i's views as one n-bit map
             bool busy = mine && e < re;
+            // the row's first two ids come from head (no row access): most
+            // vertices of a wide frontier find their parent among them
+            if (busy) {
+                const int32_t nk = re - e < 2 ? (int32_t)(re - e) : 2;
+                const uint32_t c0 = hd.x, c1 = nk > 1 ? hd.y : hd.x;
+                const uint64_t x0 = vw[c0 >> 6], x1 = vw[c1 >> 6];
+                uint32_t hm = (uint32_t)((x0 >> (c0 & 63)) & 1) | ((uint32_t)((x1 >> (c1 & 63)) & 1) << 1);
+                hm &= (1u << nk) - 1u;
+                if (hm) {
+                    const int hit = __builtin_ctz(hm);
+                    found = (int32_t)(hit ? c1 : c0);
+                    busy = false;
+                    read += (unsigned long long)(hit + 1);
+                } else {
+                    read += (unsigned long long)nk;
+                    e += nk;
+                    if (e >= re) busy = false;
+                }
+            }
             // kPullWindow entries of the row are loaded at once (positions past
             // the row end clamped to its last entry) and tested kPullUnroll at a
             // time, hits past the end masked out: the loads need no per-entry
@@ -1200,6 +1222,7 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
     pa.view = w.view;
     pa.pull_off = g->pull_off;
     pa.pull_col = g->pull_col;
+    pa.head = g->head;
     pa.level = level;
     pa.mf = w.exp_mf;
     pa.parent = parent;
@@ -1632,8 +1655,10 @@ extern "C" int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uin
     e->mb.dev = (unsigned long long *)dev;
     if (flags & CSBFS_FLAG_TIMING) {
         e->events.assign((size_t)max_levels * kEvPerLevel2, nullptr);
+        // timestamps only: no system-scope fence at each record, which would
+        // write the caches back between the kernels being timed
         for (auto &ev : e->events) {
-            herr = hipEventCreate(&ev);
+            herr = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);
             if (herr != hipSuccess) {
                 ev = nullptr;
                 engine_release(e.release());

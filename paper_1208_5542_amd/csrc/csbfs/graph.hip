@@ -210,21 +210,32 @@ __global__ void k_count_m(const int32_t *level, const int32_t *deg, int64_t n,
 
 // Merge the rows of v in blocks (j, i), j = P-1 down to 0, into one row of
 // global ids: each block row is already in decreasing order and block j
-// holds the ids of R_j, so the merged row is in decreasing order. One
+// holds the ids of R_j, so the merged row is in decreasing order. The row's
+// first two ids are also kept beside each other per vertex (head; 0xFFFFFFFF
+// where the row is shorter), so a pull can test them without the row. One
 // thread per vertex (setup only).
 __global__ void k_pull_fill(const int32_t *row_ptr, const int64_t *col_base, const uint32_t *col,
-                            int64_t R, int32_t P, int64_t n, const int64_t *pull_off, uint32_t *pull_col) {
+                            int64_t R, int32_t P, int64_t n, const int64_t *pull_off, uint32_t *pull_col,
+                            uint32_t *head) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = v / R, vl = v - i * R;
-        int64_t d = pull_off[v];
+        const int64_t d0 = pull_off[v];
+        int64_t d = d0;
+        uint32_t h[2] = {0xFFFFFFFFu, 0xFFFFFFFFu};
         for (int32_t j = P - 1; j >= 0; --j) {
             const int64_t b = (int64_t)j * P + i;
             const int32_t *rp = row_ptr + b * (R + 1) + vl;
             const uint32_t *src = col + col_base[b];
             const uint32_t base = (uint32_t)(j * R);
-            for (int32_t e = rp[0]; e < rp[1]; ++e) pull_col[d++] = base + src[e];
+            for (int32_t e = rp[0]; e < rp[1]; ++e) {
+                const uint32_t id = base + src[e];
+                if (d - d0 < 2) h[d - d0] = id;
+                pull_col[d++] = id;
+            }
         }
+        head[2 * v] = h[0];
+        head[2 * v + 1] = h[1];
     }
 }
 
@@ -279,6 +290,7 @@ int graph_layout(int64_t n, int64_t n_tuples, int32_t p, GraphLayout *L) {
     g.deg = take(4 * n);
     g.pull_off = take(8 * (n + 1));
     g.pull_col = take(4 * g.nnz);
+    g.head = take(8 * n);
     g.live = take(8 * (n / 64));
     g.qoff = take(8 * (g.P + 1));
     g.small = take(8 * 64);
@@ -340,6 +352,7 @@ extern "C" int csbfs_graph_build_into(const int64_t *src, const int64_t *dst, in
     g->deg = (int32_t *)(gm + L.deg);
     g->pull_off = (int64_t *)(gm + L.pull_off);
     g->pull_col = (uint32_t *)(gm + L.pull_col);
+    g->head = (uint32_t *)(gm + L.head);
     g->live = (uint64_t *)(gm + L.live);
     g->qoff = (int64_t *)(gm + L.qoff);
     g->scratch = (unsigned long long *)(gm + L.small);
@@ -411,7 +424,7 @@ extern "C" int csbfs_graph_build_into(const int64_t *src, const int64_t *dst, in
     if (rc) return rc;
     hipLaunchKernelGGL(k_pull_fill, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, st,
                        (const int32_t *)g->row_ptr, (const int64_t *)g->col_base, (const uint32_t *)g->col, R, p,
-                       n, (const int64_t *)g->pull_off, g->pull_col);
+                       n, (const int64_t *)g->pull_off, g->pull_col, g->head);
     CSBFS_HIP(hipGetLastError());
     std::vector<unsigned long long> tail(kMiscWords + p);
     int64_t pull_total = -1;

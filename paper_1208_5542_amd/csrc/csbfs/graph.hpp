@@ -30,7 +30,7 @@ inline int64_t big_items_bound(int64_t nnz) { return nnz / kBigChunk + nnz / kBi
 struct GraphLayout {
     int64_t n, P, R, W, B, nnz, ntile;
     // graph buffer
-    int64_t row_ptr, col_base, col, dir, deg, pull_off, pull_col, live, qoff, small, graph_bytes;
+    int64_t row_ptr, col_base, col, dir, deg, pull_off, pull_col, head, live, qoff, small, graph_bytes;
     // build scratch
     int64_t cnt, sums, nnzb, misc, queues, scan, scratch_bytes;
 };
@@ -62,6 +62,7 @@ struct csbfs_graph {
     // column v of its block-row; by symmetry the same entries as the blocks)
     int64_t *pull_off = nullptr;      // [n + 1]
     uint32_t *pull_col = nullptr;     // [nnz]
+    uint32_t *head = nullptr;         // [2n]: the first two ids of v's merged row (0xFFFFFFFF: none)
     uint64_t *live = nullptr;         // [n / 64]: vertices with at least one adjacency entry
     int64_t *qoff = nullptr;          // [P + 1]: processor r's chunk-queue region
     unsigned long long *scratch = nullptr;  // small reduction scratch
