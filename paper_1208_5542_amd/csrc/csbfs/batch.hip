@@ -262,6 +262,7 @@ struct BPullArgs {
     const uint64_t *fm;        // [n]: frontier masks of the level
     const int64_t *pull_off;   // merged rows (global ids) of every vertex
     const uint32_t *pull_col;
+    const uint32_t *head;      // [2n]: the first two ids of each merged row
     uint64_t *view;            // every view plane, zeroed here (the decode ORs into zeroed views)
     int64_t view_words;
     int64_t n;
@@ -287,14 +288,25 @@ __global__ __launch_bounds__(kBThreads) void bpull_kernel(BPullArgs a) {
         const int64_t v = v0 + lane;
         uint64_t missing = 0, found = 0;
         int64_t e = 0, re = 0;
+        uint2 hd = make_uint2(0u, 0u);
         if (v < a.n) {
             missing = active & ~a.vn[2 * v];
             if (missing) {
                 e = a.pull_off[v];
                 re = a.pull_off[v + 1];
+                hd = *reinterpret_cast<const uint2 *>(a.head + 2 * v);
             }
         }
         bool busy = missing && e < re;
+        // the row's first two ids come from head, without the row itself
+        if (busy) {
+            const int32_t nk = re - e < 2 ? (int32_t)(re - e) : 2;
+            const uint64_t m0 = a.fm[hd.x], m1 = a.fm[nk > 1 ? hd.y : hd.x];
+            found |= (m0 | m1) & missing;
+            read += (unsigned long long)nk;
+            e += nk;
+            if (found == missing || e >= re) busy = false;
+        }
         for (int round = 0; round < kBPullRounds; ++round) {
             if (busy) {
                 // every lane reads kBPullUnroll entries, positions past the row end
@@ -812,6 +824,7 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
     pa.fm = e->fm;
     pa.pull_off = g->pull_off;
     pa.pull_col = g->pull_col;
+    pa.head = g->head;
     pa.view = e->view;
     pa.view_words = B * vplane;
     pa.n = n;

@@ -318,6 +318,7 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
     __shared__ int sh_last_cls;
     __shared__ uint64_t sh_prefix;
     __shared__ bool sh_reset;
+    __shared__ int sh_clean_words;
     if (plane_skipped(b, s)) {
         if (first && threadIdx.x == 0) b.n_words[s] = 0;
         return;
@@ -377,17 +378,28 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
             prev = c;
         }
     }
-    int seg_words = 0;
-    const int base = block_excl_scan(nflag, &seg_words);
-    {
+    int seg_words = 0, base = 0;
+    if (clean) {
+        // only thread 0 can start a word (at the segment's first group)
+        if (threadIdx.x == 0) {
+            sh_clean_words = nflag;
+            if (nflag) {
+                sh_last_cls = cls[0];
+                starts[0] = (int)xa;
+            }
+        }
+        __syncthreads();
+        seg_words = sh_clean_words;
+    } else {
+        base = block_excl_scan(nflag, &seg_words);
         int pos = base;
         for (int k = 0; k < kGpt; ++k) {
             if (cls[k] < 0) continue;
             if (pos == seg_words - 1) sh_last_cls = cls[k];
             starts[pos++] = (int)(xa + k);
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     unsigned long long *look = b.look + s * b.nseg;
     // a clean segment that starts no word and is not the last writes nothing:
@@ -457,13 +469,17 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
     }
 
     // statistics: set bits after the sieve, words of the unsieved piece
-    long long tot = block_reduce(ones, SumI64(), 0LL);
-    int ucnt = 0;
-    if (unsieved) {
-        int uf = clean_uflag, ufirst;
-        long long uones;
-        if (!clean && xa < g.x1) classify(su, g, xa, xb, uf, ufirst, uones);
-        ucnt = block_reduce(uf, SumI32(), 0);
+    // (a clean segment has no ones, and only thread 0 may count an unsieved word)
+    long long tot = 0;
+    int ucnt = clean_uflag;
+    if (!clean) {
+        tot = block_reduce(ones, SumI64(), 0LL);
+        if (unsieved) {
+            int uf = 0, ufirst;
+            long long uones;
+            if (xa < g.x1) classify(su, g, xa, xb, uf, ufirst, uones);
+            ucnt = block_reduce(uf, SumI32(), 0);
+        }
     }
     if (threadIdx.x == 0) {
         if (g.last && g.r > 0 && !clean) tot += __popcll(active_word(sw, g));
