@@ -157,21 +157,34 @@ __device__ __forceinline__ SegGeom seg_geom(const WahBatch &b, int64_t seg) {
 }
 
 // Stage the segment's words (sieved, and optionally unsieved) into LDS; the
-// hook gives word w of sender i's piece in plane r before the sieve.
-template <class Hook>
+// hook gives word w of sender i's piece in plane r before the sieve. A thread
+// loads all its words (at most kIt) and their directory words before it
+// uses any, so the loads of a segment overlap instead of forming a chain.
+template <int kIt, class Hook>
 __device__ __forceinline__ void stage(const WahBatch &b, int64_t s, const SegGeom &g, uint64_t *sw,
                                       uint64_t *su, const Hook &h) {
     const StreamIdx x = stream_idx(s, b.P);
     const int64_t i = x.i, j = x.j;
     const uint64_t *mask = b.mask_base ? b.mask_base + (j * b.P + i) * b.words_per_piece : nullptr;
     const int tail = (int)(b.nbits & 63);
-    for (int64_t k = threadIdx.x; k < g.nload; k += blockDim.x) {
+    uint64_t v[kIt], m[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t k = threadIdx.x + (int64_t)it * blockDim.x;
         const int64_t w = g.wlo + k;
-        uint64_t v = h.load(b, x.r, i, w);
-        if (tail && w == b.words_per_piece - 1) v &= (1ull << tail) - 1;
-        if (su) su[k] = v;
-        if (mask && v) v &= mask[w];  // a zero word needs no directory word
-        sw[k] = v;
+        v[it] = k < g.nload ? h.load(b, x.r, i, w) : 0;
+        m[it] = (mask && k < g.nload) ? mask[w] : ~0ull;
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t k = threadIdx.x + (int64_t)it * blockDim.x;
+        if (k < g.nload) {
+            const int64_t w = g.wlo + k;
+            uint64_t vv = v[it];
+            if (tail && w == b.words_per_piece - 1) vv &= (1ull << tail) - 1;
+            if (su) su[k] = vv;
+            sw[k] = vv & m[it];
+        }
     }
     __syncthreads();
 }
@@ -342,7 +355,7 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
     // not clean too. Nothing is staged.
     const bool clean = hook.clean(b, seg, x);
     int clean_uflag = 0;
-    if (!clean) stage(b, s, g, sw, unsieved ? su : nullptr, hook);
+    if (!clean) stage<(kLds + kEncThreads - 1) / kEncThreads>(b, s, g, sw, unsieved ? su : nullptr, hook);
 
     const int64_t xa = g.x0 + (int64_t)threadIdx.x * kGpt;
     const int64_t xb = xa + kGpt < g.x1 ? xa + kGpt : g.x1;
