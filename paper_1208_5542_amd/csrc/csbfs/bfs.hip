@@ -768,12 +768,16 @@ struct FrontierHook {
                 if (mark_old.word_marked(base + q)) vw[q] = 0;
         }
         const int64_t nsteps = (q1 - q0 + kUpdWords - 1) / kUpdWords;
+        const int64_t wstride = (int64_t)P * (nt >> 6);  // steps between one wave's consecutive steps
+        constexpr int kSlots = 64 / kUpdWords;           // the wave's steps taken at once
         unsigned long long cnt = 0, dsum = 0;
-        for (int64_t c = x.j + (int64_t)P * (t >> 6); c < nsteps; c += (int64_t)P * (nt >> 6)) {
-            const int64_t qa = q0 + c * kUpdWords;
-            const int64_t qk = qa + lane;
+        // lane = step slot * kUpdWords + word: all of a wave's loads of
+        // kSlots steps are issued together rather than step after step
+        for (int64_t cb = x.j + (int64_t)P * (t >> 6); cb < nsteps; cb += wstride * kSlots) {
+            const int64_t c = cb + (int64_t)(lane / kUpdWords) * wstride;
+            const int64_t qk = q0 + c * kUpdWords + (lane % kUpdWords);
             uint64_t tk = 0;
-            if (lane < kUpdWords && qk < q1) {
+            if (c < nsteps && qk < q1) {
                 if (mark_cur.word_marked(base + qk)) {
                     tk = N_cur[base + qk];
                     if (tk) pi[base + qk] |= tk;
@@ -782,19 +786,31 @@ struct FrontierHook {
                 cnt += (unsigned long long)__popcll(tk);
             }
             if (!write_levels || !__ballot(tk != 0)) continue;
-            int32_t d[kUpdWords];
+            // levels and adjacency entries of the new vertices, kUpdWords
+            // words at a time (lane = vertex of the word)
+            for (int gs = 0; gs < kSlots; ++gs) {
+                uint64_t tw[kUpdWords];
+                uint64_t any = 0;
 #pragma unroll
-            for (int k = 0; k < kUpdWords; ++k) {
-                d[k] = 0;
-                const uint64_t tw = readlane64(tk, k);
-                if ((tw >> lane) & 1) {
-                    const int64_t v = ((base + qa + k) << 6) + lane;
-                    d[k] = deg[v];
-                    level[v] = lvl;
+                for (int k = 0; k < kUpdWords; ++k) {
+                    tw[k] = readlane64(tk, gs * kUpdWords + k);
+                    any |= tw[k];
                 }
-            }
+                if (!any) continue;
+                int32_t d[kUpdWords];
 #pragma unroll
-            for (int k = 0; k < kUpdWords; ++k) dsum += (unsigned long long)d[k];
+                for (int k = 0; k < kUpdWords; ++k) {
+                    d[k] = 0;
+                    if ((tw[k] >> lane) & 1) {
+                        const int64_t qw = (int64_t)readlane64((uint64_t)qk, gs * kUpdWords + k);
+                        const int64_t v = ((base + qw) << 6) + lane;
+                        d[k] = deg[v];
+                        level[v] = lvl;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kUpdWords; ++k) dsum += (unsigned long long)d[k];
+            }
         }
         for (int dd = 32; dd > 0; dd >>= 1) {
             cnt += (unsigned long long)shfl64((int64_t)cnt, lane ^ dd);
