@@ -684,7 +684,7 @@ __device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsign
     *a.rec = next;
 }
 
-constexpr int64_t kDecGridChunks = 16;  // decode workgroups per stream (each loops over chunks)
+constexpr int64_t kDecGridChunks = 8;  // decode workgroups per stream, each looping over chunks (8 beat 16, 32, 64)
 constexpr int kUpdWords = 8;  // bitmap words per wavefront step of the update (8 beat 4, 16, 32)
 // Groups per encoder thread of a search: 2 (segments of 1024 groups) when
 // segments of 2048 would leave fewer than two workgroups per CU, else 4.
@@ -763,9 +763,21 @@ struct FrontierHook {
         const int64_t q1 = seg_end(b, seg);
         const int64_t base = x.i * W;
         if (clear_views) {
+            // one 64-word block per wave at a time (lane = word); the marks of
+            // 64 of the wave's blocks are loaded at once first
             uint64_t *vw = view + (x.j * P + x.i) * W;
-            for (int64_t q = q0 + t; q < q1; q += nt)
-                if (mark_old.word_marked(base + q)) vw[q] = 0;
+            const int wv = t >> 6, nwv = nt >> 6;
+            const int64_t k0 = (base + q0) >> kMarkShift, k1 = (base + q1 - 1) >> kMarkShift;
+            for (int64_t kb = k0 + wv; kb <= k1; kb += (int64_t)nwv * 64) {
+                const int64_t mk = kb + (int64_t)lane * nwv;
+                uint64_t todo = __ballot(mk <= k1 && mark_old.m[mk] != 0);
+                while (todo) {
+                    const int sl = __ffsll((unsigned long long)todo) - 1;
+                    todo &= todo - 1;
+                    const int64_t q = ((kb + (int64_t)sl * nwv) << kMarkShift) + lane - base;
+                    if (q >= q0 && q < q1) vw[q] = 0;
+                }
+            }
         }
         const int64_t nsteps = (q1 - q0 + kUpdWords - 1) / kUpdWords;
         const int64_t wstride = (int64_t)P * (nt >> 6);  // steps between one wave's consecutive steps
