@@ -37,7 +37,7 @@ def test_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
 def test_committed_counters_are_consistent():
     with open(bench.COUNTERS) as f:
         d = json.load(f)
-    assert "rmat22_p4" in d
+    assert "rmat26_p8" in d  # the default workload of the bench line
     for name, ent in d.items():
         assert os.path.exists(os.path.join(bench.REPO, ent["summary"])), name
         parts = ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"]
