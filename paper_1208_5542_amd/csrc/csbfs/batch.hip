@@ -788,6 +788,8 @@ extern "C" int csbfs_batch_bfs(csbfs_batch_engine *e, const int64_t *roots, int3
     CSBFS_HIP(hipMemsetAsync(e->counters_mem, 0, e->counters_bytes, st));
     CSBFS_HIP(hipMemsetAsync(e->status, 0, sizeof(int32_t), st));
     CSBFS_HIP(hipMemsetAsync(e->qcount, 0, sizeof(uint32_t) * P, st));
+    // the encoder's tickets count on over the batch's levels: start them at zero
+    CSBFS_HIP(hipMemsetAsync(e->look, 0, e->look_bytes, st));
     CSBFS_HIP(hipMemcpyAsync(e->roots_dev, roots, sizeof(int64_t) * B, hipMemcpyHostToDevice, st));
     BSeedArgs sa{e->vn, e->fm, e->view, B * vplane, level, B * n, n};
     // evaluation of each level: top-down, bottom-up, or chosen on the device

@@ -263,10 +263,18 @@ __device__ __forceinline__ bool plane_skipped(const WahBatch &b, int64_t s) {
 // state 2 the inclusive prefix through it. A value is (count of word-starting
 // groups, the last of them, its class) and prefixes combine by adding the
 // counts and keeping the later last group.
+//
+// Launches of one stream's encoder follow each other without clearing
+// anything: its ticket counts on (every launch takes nseg tickets, so ticket
+// t is segment t % nseg of the stream's launch t / nseg), and every word
+// carries the parity of that launch number. Each launch rewrites all of its
+// stream's words, so a word of the other parity is the last launch's and
+// reads as not yet published.
 constexpr int kLbBits = 29;  // count and group-index fields: at most 2^29 - 1 groups
 constexpr uint64_t kLbField = (1ull << kLbBits) - 1;
 constexpr uint64_t kLbAgg = 1ull << 62, kLbInc = 2ull << 62;
 constexpr uint64_t kLbHasLast = 1ull << 60;
+constexpr uint64_t kLbEpoch = 1ull << 61;  // parity of the stream's launch
 constexpr uint64_t kLbLastMask = (kLbField << kLbBits) | (3ull << (2 * kLbBits)) | kLbHasLast;
 constexpr uint32_t kLbSpinLimit = 1u << 22;  // polls of one look-back window
 
@@ -276,23 +284,26 @@ __device__ __forceinline__ uint64_t lb_value(int64_t cnt, int64_t last, int cls)
 
 // Exclusive prefix of segment seg (> 0) of one stream, by wave 0: windows of
 // up to 64 earlier segments are read at once, each lane waiting for its
-// segment to publish, until a window holds an inclusive prefix.
-__device__ uint64_t lb_prefix(const WahBatch &b, unsigned long long *look, int64_t seg) {
+// segment to publish in this launch (parity ep), until a window holds an
+// inclusive prefix.
+__device__ uint64_t lb_prefix(const WahBatch &b, unsigned long long *look, int64_t seg, uint64_t ep) {
     const int lane = threadIdx.x & 63;
     int64_t cnt = 0;
     uint64_t last = 0;
+    auto ready = [ep](uint64_t v) { return (v >> 62) != 0 && (v & kLbEpoch) == ep; };
     for (int64_t k0 = seg - 1;; k0 -= 64) {
         const int64_t k = k0 - lane;
         // lanes before segment 0 hold an empty inclusive prefix
-        uint64_t v = k >= 0 ? __hip_atomic_load(&look[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kLbInc;
+        uint64_t v = k >= 0 ? __hip_atomic_load(&look[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : (kLbInc | ep);
         uint32_t polls = 0;
-        while (__ballot((v >> 62) == 0)) {
+        while (__ballot(!ready(v))) {
             if (++polls == kLbSpinLimit) {  // a lost publication: flag the stream, stop waiting
                 if (lane == 0 && b.status) *b.status = 1;
-                if ((v >> 62) == 0) v = kLbInc;
+                if (!ready(v)) v = kLbInc | ep;
                 break;
             }
-            if ((v >> 62) == 0) v = __hip_atomic_load(&look[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!ready(v)) v = __hip_atomic_load(&look[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         const uint64_t inc = __ballot((v >> 62) == 2);
         const int stop = inc ? __ffsll((unsigned long long)inc) - 1 : 63;
@@ -312,8 +323,8 @@ __device__ uint64_t lb_prefix(const WahBatch &b, unsigned long long *look, int64
 // a segment ends at a later segment's first word-starting group, so the
 // segment holding that group (or the last segment, which ends every run)
 // writes the fill word; the look-back carries its start and class. The last
-// workgroup of a stream to finish clears the stream's look-back words and
-// tickets for the next launch.
+// workgroup's ticket gives its segment and the parity of this launch of the
+// stream (see the look-back words above).
 //
 // The hook stages the words (Hook::load), may do other work with waves 1..
 // while wave 0 looks back (Hook::side), and finishes that work with thread 0
@@ -327,25 +338,22 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
     __shared__ uint64_t sw[kLds];
     __shared__ uint64_t su[kLds];
     __shared__ int starts[kSeg];
-    __shared__ int64_t sh_seg;
     __shared__ int sh_last_cls;
     __shared__ uint64_t sh_prefix;
-    __shared__ bool sh_reset;
+    __shared__ uint32_t sh_ticket;
     __shared__ int sh_clean_words;
     if (plane_skipped(b, s)) {
         if (first && threadIdx.x == 0) b.n_words[s] = 0;
         return;
     }
     // segments in the order the workgroups start, so every awaited one runs
-    uint32_t *ticket = b.ticket + s * kTicketStride;  // [0] segments started, [1] finished
-    if (threadIdx.x == 0) sh_seg = atomicAdd(&ticket[0], 1u);
+    uint32_t *ticket = b.ticket + s * kTicketStride;  // segments started, over all launches
+    if (threadIdx.x == 0) sh_ticket = atomicAdd(&ticket[0], 1u);
     hook.init();
     __syncthreads();
-    const int64_t seg = sh_seg;
-    if (seg >= b.nseg) {  // scratch not zero at launch: refuse the stream
-        if (threadIdx.x == 0 && b.status) *b.status = 1;
-        return;
-    }
+    const uint32_t tk = sh_ticket;
+    const int64_t seg = (int64_t)(tk % (uint32_t)b.nseg);
+    const uint64_t ep = ((tk / (uint32_t)b.nseg) & 1u) ? kLbEpoch : 0;
     const StreamIdx x = stream_idx(s, b.P);
     const bool unsieved = b.stat_unsieved_words && x.i == x.j;
     const SegGeom g = seg_geom<kSeg>(b, seg);
@@ -422,21 +430,21 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
         const uint64_t mine = lb_value(seg_words, seg_words ? starts[seg_words - 1] : 0, sh_last_cls);
         if (quiet) {
             if (threadIdx.x == 0) {
-                __hip_atomic_store(&look[seg], mine | kLbAgg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&look[seg], mine | kLbAgg | ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sh_prefix = 0;
             }
         } else if (seg == 0) {
             if (threadIdx.x == 0) {
-                __hip_atomic_store(&look[0], mine | kLbInc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&look[0], mine | kLbInc | ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sh_prefix = 0;
             }
         } else {
             if (threadIdx.x == 0)
-                __hip_atomic_store(&look[seg], mine | kLbAgg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t pre = lb_prefix(b, look, seg);
+                __hip_atomic_store(&look[seg], mine | kLbAgg | ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t pre = lb_prefix(b, look, seg, ep);
             if (threadIdx.x == 0) {
                 const uint64_t inc = ((pre & kLbField) + seg_words) | (seg_words ? (mine & kLbLastMask) : (pre & kLbLastMask));
-                __hip_atomic_store(&look[seg], inc | kLbInc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&look[seg], inc | kLbInc | ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sh_prefix = pre;
             }
         }
@@ -502,17 +510,6 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
             if (words) atomicAdd(&b.stat_unsieved_words[x.r * b.P + x.i], (unsigned long long)words);
         }
         hook.finish(b, s, seg);
-        // every look-back of the stream has returned once all its segments count here
-        sh_reset = atomicAdd(&ticket[1], 1u) == (uint32_t)(b.nseg - 1);
-    }
-    __syncthreads();
-    if (sh_reset) {
-        for (int64_t k = threadIdx.x; k < b.nseg; k += blockDim.x)
-            __hip_atomic_store(&look[k], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (threadIdx.x == 0) {
-            __hip_atomic_store(&ticket[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
     }
 }
 
