@@ -507,8 +507,8 @@ def main():
     inv_ratio, nlev = 0.0, 0
     # per kernel: algorithmic bytes (the formulas of expansion_bytes and
     # codec_bytes), event time, launches; the expansion also by direction
-    kern = {k: [0, 0.0, 0] for k in ("expansion", "top_down", "bottom_up", "encode", "decode")}
-    dir_count = {"top_down": 0, "bottom_up": 0}
+    kern = {k: [0, 0.0, 0] for k in ("expansion", "top_down", "top_down_binned", "bottom_up", "encode", "decode")}
+    dir_count = {"top_down": 0, "bottom_up": 0, "top_down_binned": 0}
     # the search forms f^k inside the encoder of its messages: one category
     cat_ms = {"expand": 0.0, "update_compress": 0.0, "decode": 0.0}
     R = n // p
@@ -523,7 +523,11 @@ def main():
             t = s["ms_expand"] + s["ms_long_rows"]
             d = "bottom_up" if s["direction"] == csbfs.DIR_BOTTOM_UP else "top_down"
             dir_count[d] += 1
-            for key in ("expansion", d):
+            keys = ["expansion", d]
+            if d == "top_down" and s["push"] == csbfs.PUSH_BINNED:
+                dir_count["top_down_binned"] += 1
+                keys.append("top_down_binned")  # a subset of top_down
+            for key in keys:
                 kern[key][0] += b
                 kern[key][1] += t
                 kern[key][2] += 1
@@ -624,13 +628,15 @@ def main():
                                  "receives over one whole search"},
         "roofline": {"bound": "hbm",
                      "kernel": "expansion step of one level: level_kernel (top-down push or bottom-up pull, "
-                               "chosen per level) + expand_big_kernel (top-down long rows); time = the two "
+                               "chosen per level) + expand_big_kernel (top-down long rows; on binned levels "
+                               "their pairs go into bins) + bin_resolve_kernel (binned levels); time = the "
                                "kernels' own HIP-event intervals on the library's stream",
                      "achieved": exp["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp["frac"],
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": exp["algorithmic_bytes_per_launch"],
                      "avg_launch_ms": exp["avg_launch_ms"],
-                     "by_direction": {"top_down": rate("top_down"), "bottom_up": rate("bottom_up")},
+                     "by_direction": {"top_down": rate("top_down"), "bottom_up": rate("bottom_up"),
+                                      "top_down_binned": rate("top_down_binned")},
                      "other_kernels": {"frontier_encode_kernel (update + sieve + compress)": rate("encode"),
                                        "search_decode_kernel (decode/merge + reduction)": rate("decode")}},
         "wall_s": round(wall, 3),

@@ -195,13 +195,33 @@ typedef struct csbfs_engine csbfs_engine;
 #define CSBFS_FLAG_SPARSE_ONLY 8u
 #define CSBFS_FLAG_DENSE_ONLY 16u
 #define CSBFS_FLAG_BOTTOM_UP_ONLY 32u
+/* How a top-down level applies its (target, source) pairs. The atomic push
+ * relaxes each pair in place: an atomicMax into parent[] and an atomicOr
+ * into the new-vertex bitmap, random accesses that go to the memory side.
+ * The binned push (propagation blocking, Beamer, Asanovic and Patterson,
+ * IPDPS 2017) relaxes the short rows so but writes the pairs of the long
+ * rows (over 128 entries in a block), sorted in on-chip memory, into one
+ * bin per 2^15 target vertices, then resolves each bin in on-chip memory:
+ * from the parents the atomic part left, the highest source per target,
+ * and the new vertices' parents and bitmap words, each written once. Both
+ * give identical results. By default a top-down level is binned when its
+ * frontier has at least 2^23 adjacency entries, at least 64 per frontier
+ * vertex, and at most half the bins' capacity; the workspace has bins only
+ * for graphs of at most 2^26 vertices whose half capacity is at least 2^24
+ * pairs (by default an nnz of about 2^28 or more). Pairs past a segment's
+ * capacity go to the atomic push. BINNED_PUSH bins every top-down level that
+ * fits the bins (and always gives a workspace bins); ATOMIC_PUSH never bins
+ * and the workspace holds no bins. */
+#define CSBFS_FLAG_BINNED_PUSH 64u
+#define CSBFS_FLAG_ATOMIC_PUSH 128u
 
 /*
  * Parameters of one search on a caller workspace (csbfs_bfs_ws); a zeroed
  * struct (or NULL) gives the defaults.
- *   flags           CSBFS_FLAG_KEEP_STREAMS, NO_SIEVE and at most one of
- *                   SPARSE_ONLY, DENSE_ONLY, BOTTOM_UP_ONLY (TIMING is an
- *                   engine feature and is rejected here).
+ *   flags           CSBFS_FLAG_KEEP_STREAMS, NO_SIEVE, at most one of
+ *                   SPARSE_ONLY, DENSE_ONLY, BOTTOM_UP_ONLY and at most one
+ *                   of BINNED_PUSH, ATOMIC_PUSH (TIMING is an engine
+ *                   feature and is rejected here).
  *   max_levels      levels whose counters (and, with KEEP_STREAMS, streams)
  *                   are kept, 1..65536; 0 means 64. Deeper searches still run
  *                   to the end; their extra levels are not reported.
@@ -210,7 +230,11 @@ typedef struct csbfs_engine csbfs_engine;
  *                   top-down; beta >= 0.
  *   segment_groups  groups of 63 bits per encoder segment: 1024 or 2048, or
  *                   0 to choose from the sizes (same streams either way).
- *   reserved        0.
+ *   push_bin_pairs  capacity of the binned push in (target, source) pairs
+ *                   (8 bytes each, split evenly over the bins and over 256
+ *                   segments per bin), >= 0; 0 means nnz / 8 + 65536 (nnz:
+ *                   adjacency entries). A level is binned only if its
+ *                   frontier's entries fit. Ignored with ATOMIC_PUSH.
  */
 typedef struct csbfs_search_config {
     uint32_t flags;
@@ -218,7 +242,7 @@ typedef struct csbfs_search_config {
     float alpha;
     float beta;
     int32_t segment_groups;
-    int32_t reserved;
+    int32_t push_bin_pairs;
 } csbfs_search_config;
 
 /* Byte sizes of the caller-owned device buffers. */
@@ -253,7 +277,8 @@ int csbfs_layout_query(int64_t n, int64_t n_tuples, int32_t p, const csbfs_searc
  * 4096 vertices per level parity telling which parts of them may be
  * non-zero, the p frontier views (p * n bits), the WAH stream arena (p * p
  * streams of floor((n/p)/63) + 1 words, times max_levels with
- * CSBFS_FLAG_KEEP_STREAMS), the expansion work queue and the per-level
+ * CSBFS_FLAG_KEEP_STREAMS), the expansion work queue, the binned push's
+ * bins (none with CSBFS_FLAG_ATOMIC_PUSH) and the per-level
  * counters for up to max_levels levels (1 <= max_levels <= 65536); plus a
  * pinned two-word mailbox and, with CSBFS_FLAG_TIMING, five events per
  * level. The graph must outlive the engine. The encoder's segment size is
@@ -304,9 +329,17 @@ typedef struct csbfs_level_stats {
     float ms_decode;            /* decode/merge of the f^k messages (TIMING) */
     int32_t direction;          /* CSBFS_DIR_* used to expand f^k */
     float ms_long_rows;         /* csbfs_bfs: the top-down long-row (chunk queue) kernel of the
-                                   expansion of f^k, and the parent pull of the dense
-                                   evaluation; 0 for batched searches (TIMING) */
+                                   expansion of f^k (with the binned push: the pairs written
+                                   into the bins and the bins resolved), and the parent pull
+                                   of the dense evaluation; 0 for batched searches (TIMING) */
+    int32_t push;               /* csbfs_bfs, top-down levels: CSBFS_PUSH_BINNED if the
+                                   expansion of f^k used the binned push, else
+                                   CSBFS_PUSH_ATOMIC (and for every other level) */
+    int32_t reserved;           /* 0 */
 } csbfs_level_stats;
+
+#define CSBFS_PUSH_ATOMIC 0
+#define CSBFS_PUSH_BINNED 1
 
 /*
  * One breadth-first search from `root` (Algorithm 3; the problem statement of

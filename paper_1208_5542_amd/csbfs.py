@@ -18,8 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libcsbfs.so")
 
 OK, EINVAL, ERANGE, ENOSPACE, EHIP, EOVERFLOW, ECORRUPT = 0, -1, -2, -3, -4, -5, -6
 FLAG_TIMING, FLAG_KEEP_STREAMS, FLAG_NO_SIEVE, FLAG_SPARSE_ONLY, FLAG_DENSE_ONLY = 1, 2, 4, 8, 16
-FLAG_BOTTOM_UP_ONLY = 32
+FLAG_BOTTOM_UP_ONLY, FLAG_BINNED_PUSH, FLAG_ATOMIC_PUSH = 32, 64, 128
 DIR_TOP_DOWN, DIR_BOTTOM_UP, DIR_DENSE = 0, 1, 2
+PUSH_ATOMIC, PUSH_BINNED = 0, 1
 
 _lib = None
 
@@ -44,7 +45,8 @@ class LevelStats(ctypes.Structure):
                 ("max_rank_bytes", ctypes.c_int64), ("pulled", ctypes.c_int64),
                 ("ms_expand", ctypes.c_float), ("ms_update", ctypes.c_float),
                 ("ms_compress", ctypes.c_float), ("ms_decode", ctypes.c_float),
-                ("direction", ctypes.c_int32), ("ms_long_rows", ctypes.c_float)]
+                ("direction", ctypes.c_int32), ("ms_long_rows", ctypes.c_float),
+                ("push", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -52,7 +54,7 @@ class LevelStats(ctypes.Structure):
 
 class SearchConfig(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("max_levels", ctypes.c_int32), ("alpha", ctypes.c_float),
-                ("beta", ctypes.c_float), ("segment_groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("beta", ctypes.c_float), ("segment_groups", ctypes.c_int32), ("push_bin_pairs", ctypes.c_int32)]
 
 
 class Sizes(ctypes.Structure):
@@ -169,8 +171,8 @@ def strerror(status: int) -> str:
 
 
 def search_config(flags: int = 0, max_levels: int = 64, alpha: float = 0.0, beta: float = 0.0,
-                  segment_groups: int = 0) -> SearchConfig:
-    return SearchConfig(flags, max_levels, alpha, beta, segment_groups, 0)
+                  segment_groups: int = 0, push_bin_pairs: int = 0) -> SearchConfig:
+    return SearchConfig(flags, max_levels, alpha, beta, segment_groups, push_bin_pairs)
 
 
 def layout_query(n: int, n_tuples: int, p: int, config: SearchConfig | None = None) -> dict:

@@ -13,7 +13,10 @@
 //              top-down (sparse): every set bit u of view (i, j) is a source
 //                      whose row in block (i, j) is pushed to its targets v
 //                      in R_i; an unvisited v takes u by atomicMax into
-//                      parent[v], and its first discoverer sets its N bit;
+//                      parent[v], and its first discoverer sets its N bit
+//                      (atomic push); on wide levels the (v, u) pairs of
+//                      the long rows are instead written into bins of 2^15
+//                      targets, each resolved in LDS (binned push);
 //              bottom-up: every unvisited v of R_i reads its merged row
 //                      (global ids in decreasing order) and stops at the
 //                      first neighbour set in P_i's views: the maximum;
@@ -60,12 +63,34 @@ constexpr int32_t kDirTD = CSBFS_DIR_TOP_DOWN, kDirBU = CSBFS_DIR_BOTTOM_UP, kDi
 // host learns of it one iteration late, and that iteration costs nothing).
 constexpr int32_t kDirIdle = 3;
 
+// One chunk of a long row: its entries col[gcol, gcol + len) are the
+// targets (ids local to R_r) of source u.
 struct BigItem {
-    int32_t block;
-    int32_t u_local;
-    int32_t start;  // offsets within the block's col
-    int32_t end;
+    int64_t gcol;
+    int32_t u;      // global id of the row's source
+    uint32_t rlen;  // r << 16 | len (len <= kBigChunk, r < 64)
 };
+
+// Binned push (propagation blocking: Beamer, Asanovic and Patterson, IPDPS
+// 2017), for top-down levels whose frontier has many long rows. The short
+// rows are relaxed by the atomic push as usual; the long-row kernel takes its
+// chunk items kBinGrab at a time, turns their entries into (target v, source
+// u) pairs, sorts them in LDS by bin (2^kBinShift targets per bin) and
+// appends each run to its own segment of the bin (one segment per
+// workgroup: no global atomics). bin_resolve_kernel then takes one bin at a
+// time: the highest u per target in LDS, merged with what the atomic push
+// found, and each new vertex's parent and bitmap word written once. Random
+// atomics to the memory side become streamed pairs.
+constexpr int kBinShift = 15;
+constexpr int kBinVerts = 1 << kBinShift;
+constexpr int kBinMax = 2048;                  // bins of one graph (n <= 2^26)
+constexpr int kBinGrid = 512;                  // workgroups of the long-row kernel: segments per bin
+constexpr int kBinGrab = 16;                   // items sorted together
+constexpr int kBinBuf = kBinGrab * kBigChunk;  // their entries, at most
+constexpr int kResolveThreads = 1024;
+constexpr unsigned long long kBinMinEdges = 1ull << 23;  // default: bin levels with this many entries
+constexpr unsigned long long kBinMinDegree = 64;         // ... and this many per frontier vertex
+constexpr unsigned long long kBinNever = ~0ull;
 
 // Block marks: one uint32 per 64 words (4096 vertices) of an n-bit map
 // tells whether a level's bitmap may have a vertex there, so that the
@@ -134,6 +159,13 @@ struct ExpandArgs {
     unsigned long long *edges;
     int32_t *status;
     const int32_t *dir;        // device direction of this level; the kernels run if top-down
+    // binned push (when the level's *bin is set): the long-row kernel writes
+    // the pairs of the queued rows into the bins instead of relaxing them
+    const int32_t *bin;        // device: this level's push is binned
+    int32_t nbins;
+    uint64_t *bpairs;          // [nbins][kBinGrid][cseg]: (u << 32) | (v mod 2^kBinShift)
+    uint32_t *bseg;            // [nbins][kBinGrid]: pairs each workgroup wrote (may pass cseg)
+    int64_t cseg;
 };
 
 
@@ -251,10 +283,9 @@ __device__ __forceinline__ void expand_tile(const ExpandArgs &a, int32_t r, int6
                 } else {
                     for (int32_t c = 0; c < items; ++c) {
                         BigItem it;
-                        it.block = (int32_t)b;
-                        it.u_local = (int32_t)ul;
-                        it.start = rs + c * kBigChunk;
-                        it.end = min(rs + deg, rs + (c + 1) * kBigChunk);
+                        it.gcol = gstart + (int64_t)c * kBigChunk;
+                        it.u = u;
+                        it.rlen = ((uint32_t)r << 16) | (uint32_t)min(deg - c * kBigChunk, kBigChunk);
                         queue[pos + c] = it;
                     }
                 }
@@ -351,12 +382,179 @@ __global__ __launch_bounds__(kExpThreads) void expand_kernel(ExpandArgs a) {
     expand_body<kDense>(a);
 }
 
+// Binned push, first half, in the long-row kernel (kBinGrid workgroups):
+// grab g of all processors' chunk items (kBinGrab items each, in processor
+// order) goes to workgroup g mod kBinGrid. A grab's entries (at most kBinBuf,
+// 16 per lane) are loaded together and each pair gets its rank in its bin
+// from an LDS counter; after a scan of the counts every pair is placed in
+// bin order in LDS as a 32-bit key (bin, item, v mod 2^15) and written out,
+// consecutive lanes to consecutive slots of this workgroup's segment of the
+// bin. Pairs past a segment's capacity are relaxed by the atomic push. The
+// next grab's items are loaded while the current one is sorted. At the end
+// every workgroup records how many pairs it put in each bin.
+__device__ void bin_emit(const ExpandArgs &a) {
+    static_assert(kBinGrab <= 16 && kBinMax <= 2048 && kBinShift == 15, "key: 11 + 4 + 15 bits");
+    static_assert(kBinBuf <= 65535, "16-bit offsets");
+    constexpr int kPerLane = kBinBuf / kExpThreads;
+    constexpr int kPer = kBinMax / kExpThreads;  // bins per thread in the scan
+    __shared__ uint32_t sorted[kBinBuf];
+    __shared__ uint32_t cnt[kBinMax];
+    __shared__ uint16_t off[kBinMax], seg_fill[kBinMax];
+    __shared__ int64_t it_col[kBinGrab];
+    __shared__ int32_t it_pre[kBinGrab + 1];
+    __shared__ int32_t it_u[kBinGrab];
+    __shared__ uint32_t it_vb[kBinGrab];
+    __shared__ int64_t qbase[64];
+    __shared__ int32_t qcnt[64], gpre[65];
+    __shared__ uint32_t wsum[kExpThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t G = gridDim.x;
+    for (int b = tid; b < a.nbins; b += kExpThreads) {
+        cnt[b] = 0;
+        seg_fill[b] = 0;
+    }
+    if (wid == 0) {
+        // per processor: where its items are, how many, and the grabs before it
+        int32_t c = 0, ng = 0;
+        if (lane < a.P) {
+            const int64_t cap = a.qoff[lane + 1] - a.qoff[lane];
+            const int64_t queued = a.queue_count[lane];
+            c = (int32_t)(queued < cap ? queued : cap);
+            ng = (c + kBinGrab - 1) / kBinGrab;
+            qbase[lane] = a.qoff[lane];
+            qcnt[lane] = c;
+        }
+        const int32_t inc = wave_incl_scan_i32(ng);
+        gpre[lane + 1] = inc;
+        if (lane == 0) gpre[0] = 0;
+    }
+    __syncthreads();
+    const int64_t total = gpre[a.P];
+    // item `lane` of grab g, for lanes below kBinGrab of wave 0
+    auto fetch = [&](int64_t g, BigItem &it) -> bool {
+        if (g >= total) return false;
+        int32_t r = 0;
+        while (gpre[r + 1] <= g) ++r;
+        const int64_t idx = (g - gpre[r]) * kBinGrab + lane;
+        if (idx >= qcnt[r]) return false;
+        it = a.queue[qbase[r] + idx];
+        return true;
+    };
+    BigItem nx{};
+    bool nok = false;
+    if (wid == 0 && lane < kBinGrab) nok = fetch(blockIdx.x, nx);
+    unsigned long long edges = 0;
+    for (int64_t g = blockIdx.x; g < total; g += G) {
+        if (wid == 0) {
+            int32_t len = 0;
+            if (lane < kBinGrab && nok) {
+                it_col[lane] = nx.gcol;
+                it_u[lane] = nx.u;
+                it_vb[lane] = (nx.rlen >> 16) * (uint32_t)a.R;
+                len = (int32_t)(nx.rlen & 0xFFFFu);
+            }
+            const int32_t inc = wave_incl_scan_i32(len);
+            if (lane < kBinGrab) it_pre[lane + 1] = inc;
+            if (lane == 0) it_pre[0] = 0;
+            nok = false;
+            if (lane < kBinGrab) nok = fetch(g + G, nx);
+        }
+        __syncthreads();
+        const int32_t tot = it_pre[kBinGrab];
+        if (tid == 0) edges += (unsigned long long)tot;
+        uint32_t c[kPerLane], key[kPerLane], rank[kPerLane];
+        int32_t ix[kPerLane];
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            const int32_t e = tid + k * kExpThreads;
+            ix[k] = -1;
+            c[k] = 0;
+            if (e < tot) {
+                int32_t it = 0;
+#pragma unroll
+                for (int step = kBinGrab / 2; step > 0; step >>= 1)
+                    if (it_pre[it + step] <= e) it += step;
+                ix[k] = it;
+                c[k] = a.col[it_col[it] + (e - it_pre[it])];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            key[k] = 0;
+            rank[k] = 0;
+            if (ix[k] >= 0) {
+                const uint32_t v = it_vb[ix[k]] + c[k];
+                key[k] = ((v >> kBinShift) << 19) | ((uint32_t)ix[k] << 15) | (v & (uint32_t)(kBinVerts - 1));
+                rank[k] = atomicAdd(&cnt[v >> kBinShift], 1u);
+            }
+        }
+        __syncthreads();
+        uint32_t loc[kPer], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int b = tid * kPer + q;
+            loc[q] = b < a.nbins ? cnt[b] : 0u;
+            sum += loc[q];
+        }
+        const int incl = wave_incl_scan_i32((int)sum);
+        if (lane == 63) wsum[wid] = (uint32_t)incl;
+        __syncthreads();
+        uint32_t base = (uint32_t)incl - sum;
+        for (int w = 0; w < wid; ++w) base += wsum[w];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int b = tid * kPer + q;
+            if (b < a.nbins) off[b] = (uint16_t)base;
+            base += loc[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k)
+            if (ix[k] >= 0) sorted[off[key[k] >> 19] + rank[k]] = key[k];
+        __syncthreads();
+        for (int i = tid; i < tot; i += kExpThreads) {
+            const uint32_t kk = sorted[i], b = kk >> 19;
+            const int32_t it = (int32_t)((kk >> 15) & 15u);
+            const uint32_t vl = kk & (uint32_t)(kBinVerts - 1);
+            const int64_t slot = (int64_t)seg_fill[b] + (i - (int64_t)off[b]);
+            if (slot < a.cseg) {
+                a.bpairs[((int64_t)b * kBinGrid + blockIdx.x) * a.cseg + slot] = ((uint64_t)(uint32_t)it_u[it] << 32) | vl;
+            } else {
+                const int64_t vv[1] = {(int64_t)((b << kBinShift) | vl)};
+                const int32_t uu[1] = {it_u[it]};
+                const bool ok[1] = {true};
+                relax_batch<false, 1>(a, vv, uu, ok);
+            }
+        }
+        __syncthreads();  // sorted, off, seg_fill and the item table read
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int b = tid * kPer + q;
+            if (b < a.nbins) {
+                const uint32_t f = seg_fill[b] + loc[q];
+                seg_fill[b] = (uint16_t)(f < 65535u ? f : 65535u);  // only compared with cseg
+                cnt[b] = 0;
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < a.nbins; b += kExpThreads) a.bseg[(int64_t)b * kBinGrid + blockIdx.x] = seg_fill[b];
+    block_add<kExpThreads / 64>(edges, a.edges);
+}
+
 // Chunk-queue items (<= kBigChunk entries of one long row) of every
-// processor, strided over the grid.
+// processor, strided over the grid; with the binned push,
+// their pairs go into the bins.
 template <bool kDense>
 __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
     const int32_t d = *a.dir;
     if (d == kDirBU || d == kDirIdle) return;
+    if constexpr (!kDense) {
+        if (*a.bin) {
+            bin_emit(a);
+            return;
+        }
+    }
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -373,24 +571,22 @@ __global__ __launch_bounds__(kExpThreads) void expand_big_kernel(ExpandArgs a) {
         before += count;
         for (int64_t kk = first; kk < count; kk += nwaves) {
             const BigItem it = queue[kk];
-            const int64_t b = it.block;
-            const int32_t j = (int32_t)(b - (int64_t)r * a.P);
-            const int32_t u = (int32_t)(j * a.R + it.u_local);
-            const uint32_t *colb = a.col + a.col_base[b];
-            for (int32_t e0 = it.start; e0 < it.end; e0 += 64 * kBigUnroll) {
+            const int32_t len = (int32_t)(it.rlen & 0xFFFFu);
+            const uint32_t *colb = a.col + it.gcol;
+            for (int32_t e0 = 0; e0 < len; e0 += 64 * kBigUnroll) {
                 int64_t v[kBigUnroll];
                 int32_t uu[kBigUnroll];
                 bool ok[kBigUnroll];
 #pragma unroll
                 for (int k = 0; k < kBigUnroll; ++k) {
                     const int32_t e = e0 + 64 * k + lane;
-                    ok[k] = e < it.end;
+                    ok[k] = e < len;
                     v[k] = vbase + (ok[k] ? colb[e] : 0u);
-                    uu[k] = u;
+                    uu[k] = it.u;
                 }
                 relax_batch<kDense, kBigUnroll>(a, v, uu, ok);
             }
-            edges += (unsigned long long)(it.end - it.start);
+            edges += (unsigned long long)len;
         }
     }
     block_add<kExpThreads / 64>(edges, a.edges);
@@ -637,11 +833,125 @@ __global__ __launch_bounds__(kExpThreads) void level_kernel(ExpandArgs ea, PullA
     }
 }
 
+// Binned push, second half: bin b takes the highest source of each target
+// from the pairs of its kBinGrid segments, in LDS. A target that is
+// unvisited is new if it has such a source or the atomic push (short rows,
+// and pairs past a segment) already found it (its bit in N); then its parent
+// is the larger of the two, and its bitmap word is written once, by the wave
+// that owns the word. A bin without pairs is already complete.
+struct ResolveArgs {
+    const int32_t *dir;
+    const int32_t *bin;
+    const uint64_t *bpairs;
+    const uint32_t *bseg;
+    int64_t cseg;
+    int32_t nbins;
+    const uint64_t *pi;
+    uint64_t *N;
+    BlockMarks marks_next;
+    int32_t *parent;
+    int64_t words;
+};
+
+__global__ __launch_bounds__(kResolveThreads) void bin_resolve_kernel(ResolveArgs a) {
+    if (*a.dir != kDirTD || !*a.bin) return;
+    __shared__ int32_t best[kBinVerts];
+    __shared__ int32_t spre[kBinGrid + 1];
+    __shared__ int32_t wtot[kResolveThreads / 64];
+    constexpr int kWaves = kResolveThreads / 64;
+    constexpr int kWordsPerWave = kBinVerts / 64 / kWaves;  // 32: word wid + kWaves * k of the bin
+    constexpr int kPairUnroll = 8;
+    static_assert(kWordsPerWave <= 64, "one word per lane");
+    static_assert(kBinGrid <= kResolveThreads, "one segment count per thread");
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // segment sizes of bin b (loaded one bin ahead)
+    auto seg_size = [&](int64_t b) -> int32_t {
+        if (b >= a.nbins || tid >= kBinGrid) return 0;
+        const int64_t sz = a.bseg[b * kBinGrid + tid];
+        return (int32_t)(sz < a.cseg ? sz : a.cseg);
+    };
+    int32_t cnext = seg_size(blockIdx.x);
+    for (int64_t b = blockIdx.x; b < a.nbins; b += gridDim.x) {
+        // segment sizes and their prefix sums
+        const int32_t c = cnext;
+        cnext = seg_size(b + gridDim.x);
+        const int32_t incl = wave_incl_scan_i32(c);
+        if (lane == 63) wtot[wid] = incl;
+        __syncthreads();
+        int32_t before = 0;
+        for (int w = 0; w < wid; ++w) before += wtot[w];
+        if (tid < kBinGrid) spre[tid + 1] = before + incl;
+        if (tid == 0) spre[0] = 0;
+        __syncthreads();
+        const int32_t total = spre[kBinGrid];
+        if (total == 0) continue;  // no pair: the atomic push did all of this bin
+        const int64_t w0 = b * (kBinVerts / 64);
+        // this wave's visited and atomic-push words, one per lane
+        const int64_t myw = w0 + wid + (int64_t)kWaves * lane;
+        const bool mine = lane < kWordsPerWave && myw < a.words;
+        const uint64_t visv = mine ? a.pi[myw] : ~0ull;
+        const uint64_t nv = mine ? a.N[myw] : 0ull;
+        for (int i = tid; i < kBinVerts; i += kResolveThreads) best[i] = -1;
+        __syncthreads();
+        const uint64_t *pb = a.bpairs + b * kBinGrid * a.cseg;
+        for (int32_t i0 = 0; i0 < total; i0 += kPairUnroll * kResolveThreads) {
+            uint64_t q[kPairUnroll];
+            bool ok[kPairUnroll];
+#pragma unroll
+            for (int k = 0; k < kPairUnroll; ++k) {
+                const int32_t i = i0 + k * kResolveThreads + tid;
+                ok[k] = i < total;
+                q[k] = 0ull;
+                if (ok[k]) {
+                    int32_t sg = 0;
+#pragma unroll
+                    for (int step = kBinGrid / 2; step > 0; step >>= 1)
+                        if (spre[sg + step] <= i) sg += step;
+                    q[k] = pb[sg * a.cseg + (i - spre[sg])];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kPairUnroll; ++k)
+                if (ok[k]) atomicMax(&best[q[k] & (uint64_t)(kBinVerts - 1)], (int32_t)(q[k] >> 32));
+        }
+        __syncthreads();
+        // targets both paths reached: the atomic push's parent, all loaded first
+        int32_t pk[kWordsPerWave];
+#pragma unroll
+        for (int k = 0; k < kWordsPerWave; ++k) {
+            pk[k] = -1;
+            const int64_t gw = w0 + wid + (int64_t)kWaves * k;
+            const bool both = gw < a.words && ((readlane64(nv, k) >> lane) & 1) &&
+                              best[(wid + kWaves * k) * 64 + lane] >= 0;
+            if (both) pk[k] = a.parent[gw * 64 + lane];
+        }
+#pragma unroll
+        for (int k = 0; k < kWordsPerWave; ++k) {
+            const int64_t wl = wid + (int64_t)kWaves * k;
+            const int64_t gw = w0 + wl;
+            if (gw < a.words) {
+                const uint64_t vis = readlane64(visv, k), old = readlane64(nv, k);
+                const int32_t m = best[wl * 64 + lane];
+                const bool open = !((vis >> lane) & 1);
+                if (open && m >= 0) a.parent[gw * 64 + lane] = m > pk[k] ? m : pk[k];
+                const uint64_t bits = __ballot(open && m >= 0) | old;
+                if (lane == 0 && bits != old) {
+                    a.N[gw] = bits;
+                    a.marks_next.mark_word(gw);
+                }
+            }
+        }
+        __syncthreads();  // best, spre and wtot are used again
+    }
+}
+
 // Direction state carried from level to level on the device.
 struct DirState {
     int32_t cur;              // direction of the level expanded next
     int32_t tile;             // view words per top-down tile of that level: 64, or
                               // 16 when the frontier holds n/64 vertices or more
+    int32_t bin;              // 1: that level is top-down with the binned push
+    int32_t spare;
     unsigned long long vdeg;  // adjacency entries of the visited vertices
     unsigned long long prev;  // size of the newest frontier (compared with the next one)
 };
@@ -654,6 +964,11 @@ struct DirArgs {
     float alpha;
     float beta;
     int32_t force;  // < 0: choose by the rule; else this direction at every level
+    // a top-down level is binned when its entries are at least bin_min
+    // (kBinNever: never) and bin_deg per frontier vertex, and at most bin_cap
+    unsigned long long bin_min;
+    unsigned long long bin_deg;
+    unsigned long long bin_cap;
 };
 
 // Beamer's rule (Sec. VIII names direction optimization as the next step):
@@ -680,8 +995,10 @@ __device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsign
     s.prev = nf;
     s.cur = next;
     s.tile = (double)nf * 64.0 >= (double)a.n ? 16 : 64;
+    s.bin = next == kDirTD && a.bin_min != kBinNever && mf >= a.bin_min && mf >= a.bin_deg * nf &&
+            mf <= a.bin_cap;
     *a.st = s;
-    *a.rec = next;
+    *a.rec = next | (s.bin << 8);  // direction, and the binned push in bit 8
 }
 
 constexpr int64_t kDecGridChunks = 8;  // decode workgroups per stream, each looping over chunks (8 beat 16, 32, 64)
@@ -958,6 +1275,8 @@ __global__ void seed_root_kernel(SeedArgs a, int64_t root, int64_t R, int64_t W,
     DirState s;
     s.cur = dir0;
     s.tile = 64;
+    s.bin = 0;
+    s.spare = 0;
     s.vdeg = (unsigned long long)deg[root];
     s.prev = 1;
     *ds = s;
@@ -998,13 +1317,15 @@ struct LevelCounters {
 // search's parameters; a function of (n, p, adjacency total, config) only.
 struct SearchLayout {
     int64_t n, P, R, W, S, cap, nseg, nchunk, words, L, arena_slots, queue_cap;
+    int64_t nbins, cseg, bin_cap;  // binned push: bins, pairs per segment, pairs in all
+    unsigned long long bin_min, bin_deg, bin_limit;  // a level's entries: at least, per frontier vertex, at most
     int enc_gpt;  // groups per encoder thread: segments of 512 * enc_gpt groups
     uint32_t flags;
     float alpha, beta;
     // byte offsets
     int64_t seg_words, nmarks;  // bitmap words per encoder segment; block marks per level
-    int64_t pi, nb0, nb1, view, arena, look, look_bytes, chunk_groups, queue, part, dstate, marks, counters,
-        counters_bytes, total;
+    int64_t pi, nb0, nb1, view, arena, look, look_bytes, chunk_groups, queue, part, dstate, marks, bpairs, bseg,
+        counters, counters_bytes, total;
 };
 
 // Pointers into one workspace.
@@ -1022,12 +1343,15 @@ struct SearchState {
     LevelCounters lc;
     int32_t *status;
     uint32_t *ctrs;  // [P]: chunk-queue items pushed
+    uint64_t *bpairs;
+    uint32_t *bseg;
     uint32_t *marks[2];  // block marks by level parity: marks[k & 1] for f^k
     unsigned long long *exp_mf;  // adjacency entries of the vertices a pull found (one level)
 };
 
 constexpr uint32_t kSearchFlags = CSBFS_FLAG_KEEP_STREAMS | CSBFS_FLAG_NO_SIEVE | CSBFS_FLAG_SPARSE_ONLY |
-                                  CSBFS_FLAG_DENSE_ONLY | CSBFS_FLAG_BOTTOM_UP_ONLY;
+                                  CSBFS_FLAG_DENSE_ONLY | CSBFS_FLAG_BOTTOM_UP_ONLY | CSBFS_FLAG_BINNED_PUSH |
+                                  CSBFS_FLAG_ATOMIC_PUSH;
 
 int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *cfg, SearchLayout *out) {
     csbfs_search_config c{};
@@ -1043,7 +1367,9 @@ int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *
         return fail(CSBFS_EINVAL, "search config: alpha must be a number and beta >= 0");
     if (c.segment_groups != 0 && c.segment_groups != 1024 && c.segment_groups != 2048)
         return fail(CSBFS_EINVAL, "search config: segment_groups must be 0, 1024 or 2048");
-    if (c.reserved != 0) return fail(CSBFS_EINVAL, "search config: reserved must be 0");
+    if ((c.flags & CSBFS_FLAG_BINNED_PUSH) && (c.flags & CSBFS_FLAG_ATOMIC_PUSH))
+        return fail(CSBFS_EINVAL, "search config: BINNED_PUSH and ATOMIC_PUSH exclude each other");
+    if (c.push_bin_pairs < 0) return fail(CSBFS_EINVAL, "search config: push_bin_pairs must be >= 0");
     SearchLayout y{};
     y.n = n;
     y.P = p;
@@ -1060,6 +1386,28 @@ int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *
     y.L = c.max_levels;
     y.arena_slots = (c.flags & CSBFS_FLAG_KEEP_STREAMS) ? y.L + 1 : 1;
     y.queue_cap = big_items_bound(nnz);
+    // binned push: bins of 2^kBinShift targets, kBinGrid segments per bin, the
+    // capacity split evenly (64-byte segments). By default a level is binned
+    // only with half the capacity to spare, and only on graphs where such a
+    // level can pass the entry threshold twice over (else there are no bins,
+    // and no resolve launches); BINNED_PUSH bins any top-down level that fits.
+    // No bins with ATOMIC_PUSH or above kBinMax bins.
+    const bool forced = (c.flags & CSBFS_FLAG_BINNED_PUSH) != 0;
+    const int64_t cap0 = c.push_bin_pairs > 0 ? c.push_bin_pairs : nnz / 8 + 65536;
+    y.nbins = (n + kBinVerts - 1) >> kBinShift;
+    if ((c.flags & CSBFS_FLAG_ATOMIC_PUSH) || y.nbins > kBinMax) y.nbins = 0;
+    if (!forced && (unsigned long long)cap0 / 2 < 2 * kBinMinEdges) y.nbins = 0;
+    if (y.nbins) {
+        y.bin_cap = cap0;
+        y.cseg = ((y.bin_cap + y.nbins * kBinGrid - 1) / (y.nbins * kBinGrid) + 7) / 8 * 8;
+        y.bin_min = forced ? 0ull : kBinMinEdges;
+        y.bin_deg = forced ? 0ull : kBinMinDegree;
+        y.bin_limit = (unsigned long long)(forced ? y.bin_cap : y.bin_cap / 2);
+    } else {
+        y.bin_cap = y.cseg = 0;
+        y.bin_min = kBinNever;
+        y.bin_deg = y.bin_limit = 0;
+    }
     y.flags = c.flags;
     // Beamer's parameters of the per-level direction choice, measured best
     // on R-MAT graphs of scale 22 (4 x 4) and 26 (8 x 8)
@@ -1083,6 +1431,8 @@ int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *
     y.part = take(16 * y.S * y.nseg);
     y.dstate = take((int64_t)sizeof(DirState));
     y.marks = take(4 * 2 * y.nmarks);
+    y.bpairs = take(8 * y.nbins * kBinGrid * y.cseg);
+    y.bseg = take(4 * y.nbins * kBinGrid);
     // everything a search starts from zero, in one block the seed clears:
     // per-level counters, then the status flag and the queue counts
     const int64_t slots = y.L + 1;
@@ -1130,6 +1480,8 @@ SearchState bind_workspace(const SearchLayout &y, void *ws) {
     w.lc.dir = (int32_t *)(w.lc.words + slots * S);
     w.status = w.lc.dir + slots;
     w.ctrs = reinterpret_cast<uint32_t *>(w.status + 1);
+    w.bpairs = (uint64_t *)(b + y.bpairs);
+    w.bseg = (uint32_t *)(b + y.bseg);
     return w;
 }
 
@@ -1244,6 +1596,14 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
     ea.dir = &w.dstate->cur;
     ea.tile = &w.dstate->tile;
     ea.tile_words = 64;
+    ea.bin = &w.dstate->bin;
+    ea.nbins = (int32_t)y.nbins;
+    ea.bpairs = w.bpairs;
+    ea.bseg = w.bseg;
+    ea.cseg = y.cseg;
+    ResolveArgs rsa{&w.dstate->cur, &w.dstate->bin, w.bpairs, w.bseg, y.cseg, (int32_t)y.nbins,
+                    w.pi, nullptr, BlockMarks{nullptr}, parent, words};
+    const unsigned resolve_grid = (unsigned)std::min<int64_t>(std::max<int64_t>(y.nbins, 1), 256);
     PullArgs pa{};
     pa.pi = w.pi;
     pa.live = g->live;
@@ -1266,7 +1626,7 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
     // grids (multiples of the XCD count) from sweeps at scales 22 and 26:
     // 512 expansion workgroups of 8 waves and 256 for the long rows (the
     // same waves as 1024 and 512 of 4, which beat 512-4096 and 512-2048)
-    const unsigned exp_grid = 512, big_grid = 256;
+    const unsigned exp_grid = 512, big_grid = kBinGrid;
     const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
     const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 2048);
     pa.xcd = xcd_split(P, pull_grid) && W % kPullTileDense == 0;
@@ -1279,6 +1639,9 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
     da.alpha = y.alpha;
     da.beta = y.beta;
     da.force = force;
+    da.bin_min = y.bin_min;
+    da.bin_deg = y.bin_deg;
+    da.bin_cap = y.bin_limit;
 
     WahBatch wb{};  // the words come from FrontierHook, not from a bits buffer
     wb.mask_base = (y.flags & CSBFS_FLAG_NO_SIEVE) ? nullptr : g->dir;
@@ -1347,6 +1710,8 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
         pb.next_level = (int32_t)(j + 1);
         ea.marks_next = marks_of(j + 1);
         ea.marks_view = marks_of(j);
+        rsa.N = w.nb[(j + 1) & 1];
+        rsa.marks_next = marks_of(j + 1);
         pa.marks_next = marks_of(j + 1);
         pb.marks_next = marks_of(j + 1);
         // a1: expand f^j (tile width and direction chosen on the device)
@@ -1365,6 +1730,10 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
             if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
             hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
             CSBFS_HIP(hipGetLastError());
+            if (y.nbins) {
+                hipLaunchKernelGGL(bin_resolve_kernel, dim3(resolve_grid), dim3(kResolveThreads), 0, st, rsa);
+                CSBFS_HIP(hipGetLastError());
+            }
         } else {
             pb.edges = w.lc.edges + sj;
             pb.pulled = w.lc.pulled + sj;
@@ -1382,6 +1751,10 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
                 if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
                 hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
                 CSBFS_HIP(hipGetLastError());
+                if (y.nbins) {
+                    hipLaunchKernelGGL(bin_resolve_kernel, dim3(resolve_grid), dim3(kResolveThreads), 0, st, rsa);
+                    CSBFS_HIP(hipGetLastError());
+                }
             }
         }
         if (ev) CSBFS_HIP(hipEventRecord(ev[4], st));
@@ -1457,7 +1830,8 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
         s.frontier = (int64_t)ctl[2 * lv];
         s.edges = (int64_t)ed[lv];
         s.pulled = (int64_t)pl[lv];
-        s.direction = dr[lv];
+        s.direction = dr[lv] & 0xFF;
+        s.push = dr[lv] >> 8;
         s.view_bits = P;  // the source is set in every view at level 0
         if (lv > 0) {
             int64_t sieved = 0, sent = 0, self = 0, uws = 0, maxr = 0;

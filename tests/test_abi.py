@@ -133,7 +133,7 @@ def test_level_stats_layout_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"\b(?:int64_t|int32_t|float)\s+(\w+);", body)
     assert names == [f[0] for f in csbfs.LevelStats._fields_]
-    assert ctypes.sizeof(csbfs.LevelStats) == 11 * 8 + 4 * 4 + 2 * 4
+    assert ctypes.sizeof(csbfs.LevelStats) == 11 * 8 + 4 * 4 + 4 * 4
 
 
 def test_layout_query_is_host_only_and_exact_in_its_inputs():
@@ -158,9 +158,24 @@ def test_layout_query_is_host_only_and_exact_in_its_inputs():
     with pytest.raises(csbfs.CsbfsError) as ei:
         csbfs.layout_query(1 << 12, -1, 4)
     assert ei.value.status == csbfs.EINVAL
+    # the binned push's bins: none with ATOMIC_PUSH, nor by default on a graph
+    # this small (no level could pass the threshold twice over); with
+    # BINNED_PUSH 8 bytes per pair of capacity
+    binned = csbfs.FLAG_BINNED_PUSH
+    atomic = csbfs.layout_query(1 << 22, 1 << 26, 4, csbfs.search_config(flags=csbfs.FLAG_ATOMIC_PUSH))
+    assert atomic["workspace_bytes"] == a["workspace_bytes"]
+    small = csbfs.layout_query(1 << 22, 1 << 26, 4, csbfs.search_config(flags=binned, push_bin_pairs=1 << 20))
+    big = csbfs.layout_query(1 << 22, 1 << 26, 4, csbfs.search_config(flags=binned, push_bin_pairs=1 << 24))
+    assert atomic["workspace_bytes"] < small["workspace_bytes"] < big["workspace_bytes"]
+    assert big["workspace_bytes"] - small["workspace_bytes"] >= 8 * ((1 << 24) - (1 << 20))
+    # a graph with 2^31 entries gets bins by default
+    large = csbfs.layout_query(1 << 26, 1 << 30, 8)
+    large_atomic = csbfs.layout_query(1 << 26, 1 << 30, 8, csbfs.search_config(flags=csbfs.FLAG_ATOMIC_PUSH))
+    assert large["workspace_bytes"] - large_atomic["workspace_bytes"] >= 8 * (1 << 28)
     for bad in (csbfs.search_config(flags=csbfs.FLAG_TIMING), csbfs.search_config(flags=8 | 16),
                 csbfs.search_config(max_levels=70000), csbfs.search_config(segment_groups=512),
-                csbfs.SearchConfig(0, 64, 0.0, 0.0, 0, 1)):
+                csbfs.search_config(flags=csbfs.FLAG_BINNED_PUSH | csbfs.FLAG_ATOMIC_PUSH),
+                csbfs.SearchConfig(0, 64, 0.0, 0.0, 0, -1)):
         with pytest.raises(csbfs.CsbfsError) as ei:
             csbfs.layout_query(1 << 12, 100, 4, bad)
         assert ei.value.status == csbfs.EINVAL

@@ -123,7 +123,9 @@ def test_volume_p3_example(golden):
         assert sent == gd["rank_sent_bytes"] and recv == gd["rank_received_bytes"]
 
 
-MODES = {"auto": 0, "sparse": 8, "dense": 16, "bottom_up": 32}
+MODES = {"auto": 0, "sparse": 8, "dense": 16, "bottom_up": 32,
+         # the binned push at every top-down level (default: wide levels only)
+         "binned": 64, "binned_sparse": 8 | 64}
 
 
 @pytest.mark.parametrize("mode", list(MODES))
@@ -159,6 +161,76 @@ def test_encoder_segment_sizes(groups):
     for root in inputs.pick_roots(n, src, dst, 2, inputs.graph_seed(scale) + 2):
         log(f"search scale={scale} p={p} segment groups={groups} root={int(root)}")
         _check_search(eng, g, n, p, src, dst, int(root), adj, V)
+
+
+def test_binned_push_bin_overflow():
+    """Pairs past a bin segment's capacity go through the atomic push and the
+    bin's resolve starts from what that left: 50 sources each push 400 of the
+    same 2000 targets (rows of about 200 entries per block, so they go to the
+    long-row kernel), all in the first of the two bins of a 2^16-vertex
+    graph whose bin segments hold 48 pairs each, so most targets take their
+    highest source from both paths; parents exact against the oracle."""
+    from paper_1208_5542_amd import csbfs
+    n, p = 1 << 16, 4
+    rng = np.random.default_rng(31)
+    root = 65000
+    mids = rng.choice(np.arange(40000, 64000), 50, replace=False)
+    targets = rng.choice(np.arange(0, 1 << 15), 2000, replace=False)
+    src = [np.full(50, root), np.repeat(mids, 400)]
+    dst = [mids, np.concatenate([rng.choice(targets, 400, replace=False) for _ in mids])]
+    src.append(rng.integers(0, n, 3000))
+    dst.append(rng.integers(0, n, 3000))
+    src = np.concatenate(src).astype(np.int64)
+    dst = np.concatenate(dst).astype(np.int64)
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst).reshape(-1)
+    for flags in (csbfs.FLAG_BINNED_PUSH, csbfs.FLAG_BINNED_PUSH | csbfs.FLAG_SPARSE_ONLY):
+        eng = csbfs.WorkspaceSearch(g, csbfs.search_config(flags=csbfs.FLAG_KEEP_STREAMS | flags,
+                                                           push_bin_pairs=24000))
+        for r in (root, int(mids[0]), int(targets[0])):
+            log(f"bin overflow flags={flags} root={r}")
+            res = _check_search(eng, g, n, p, src, dst, r, adj, V)
+            if r == root and flags & csbfs.FLAG_SPARSE_ONLY:
+                # the expansion of f^1 (20000+ pairs, nearly all into one bin) was binned
+                assert res.stats[1]["direction"] == csbfs.DIR_TOP_DOWN
+                assert res.stats[1]["push"] == csbfs.PUSH_BINNED
+                assert res.stats[1]["edges"] > 20000
+
+
+def test_binned_push_default_choice():
+    """By default a top-down level is binned only with at least 2^23
+    adjacency entries, 64 per frontier vertex (and on this graph only with
+    bins for all its entries); ATOMIC_PUSH never bins, BINNED_PUSH bins every
+    top-down level that fits. Same results every way (R-MAT scale 20,
+    4 x 4), checked against the oracle."""
+    from paper_1208_5542_amd import csbfs
+    scale, p = 20, 4
+    n, src, dst = _graph(scale)
+    g = csbfs.Graph(_dev(src), _dev(dst), n, p)
+    adj = oracle.Adjacency(n, src, dst)
+    V = oracle.directory(n, p, src, dst).reshape(-1)
+    cases = {
+        "auto": csbfs.Engine(g, max_levels=64),
+        "sparse": csbfs.WorkspaceSearch(g, csbfs.search_config(flags=csbfs.FLAG_SPARSE_ONLY,
+                                                               push_bin_pairs=g.info.nnz)),
+        "atomic": csbfs.Engine(g, max_levels=64, flags=csbfs.FLAG_ATOMIC_PUSH),
+        "forced": csbfs.WorkspaceSearch(g, csbfs.search_config(flags=csbfs.FLAG_SPARSE_ONLY |
+                                                               csbfs.FLAG_BINNED_PUSH,
+                                                               push_bin_pairs=g.info.nnz)),
+    }
+    for name, eng in cases.items():
+        for root in inputs.pick_roots(n, src, dst, 2, inputs.graph_seed(scale) + 2):
+            log(f"push choice scale={scale} {name} root={int(root)}")
+            r = _check_search(eng, g, n, p, src, dst, int(root), adj, V, keep=False)
+            for k, s in enumerate(r.stats):
+                binned = s["push"] == csbfs.PUSH_BINNED
+                if name == "forced":
+                    assert binned == (k > 0), k  # level 0 (the root alone) is set up unbinned
+                elif binned:
+                    assert name != "atomic"
+                    assert s["direction"] == csbfs.DIR_TOP_DOWN and s["edges"] >= 1 << 23
+                    assert s["edges"] >= 64 * s["frontier"]
 
 
 def test_sparse_graph_many_levels():
