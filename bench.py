@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2, help="untimed roots first")
     ap.add_argument("--workload", default="rmat26_p8", help="rmat10_p1 | rmat22_p4 | rmat26_p8")
     ap.add_argument("--alpha", type=float, default=None, help="direction rule alpha (default: the library's)")
+    ap.add_argument("--beta", type=float, default=None, help="direction rule beta (default: the library's)")
     ap.add_argument("--no-sieve", action="store_true", help="Alg. 2 messages (no directory)")
     ap.add_argument("--mode", default="auto", choices=["auto", "sparse", "dense", "bottom_up"],
                     help="evaluation of each level's product (results are identical): auto = "
@@ -467,9 +468,11 @@ def main():
     # gives the byte counts, the time split and the roofline
     eng = csbfs.Engine(g, max_levels=256, flags=flags)
     probe = csbfs.Engine(g, max_levels=256, flags=flags | csbfs.FLAG_TIMING)
-    if args.alpha is not None:
-        eng.set_direction(args.alpha, 24.0)
-        probe.set_direction(args.alpha, 24.0)
+    if args.alpha is not None or args.beta is not None:
+        a_ = 16.0 if args.alpha is None else args.alpha
+        b_ = 48.0 if args.beta is None else args.beta
+        eng.set_direction(a_, b_)
+        probe.set_direction(a_, b_)
     level = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
     for r in roots[: args.warmup]:

@@ -226,7 +226,7 @@ typedef struct csbfs_engine csbfs_engine;
  *                   are kept, 1..65536; 0 means 64. Deeper searches still run
  *                   to the end; their extra levels are not reported.
  *   alpha, beta     the direction rule of csbfs_engine_set_direction; both 0
- *                   mean alpha = 16, beta = 24; alpha < 0 keeps every level
+ *                   mean alpha = 16, beta = 48; alpha < 0 keeps every level
  *                   top-down; beta >= 0.
  *   segment_groups  groups of 63 bits per encoder segment: 1024 or 2048, or
  *                   0 to choose from the sizes (same streams either way).
@@ -295,7 +295,7 @@ int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags
  * the frontier did not shrink; a
  * bottom-up search turns top-down again when |f^{k+1}| * beta < n and the
  * frontier shrank. Level 0 is top-down. alpha <= 0 keeps every level
- * top-down. Defaults: alpha = 16, beta = 24. Takes effect at the next
+ * top-down. Defaults: alpha = 16, beta = 48. Takes effect at the next
  * csbfs_bfs. Errors: EINVAL (NULL engine, beta <= 0 or a NaN).
  */
 int csbfs_engine_set_direction(csbfs_engine *e, float alpha, float beta);

@@ -858,6 +858,8 @@ __global__ __launch_bounds__(kResolveThreads) void bin_resolve_kernel(ResolveArg
     __shared__ int32_t best[kBinVerts];
     __shared__ int32_t spre[kBinGrid + 1];
     __shared__ int32_t wtot[kResolveThreads / 64];
+    constexpr int kBinMarks = kBinVerts / 64 >> kMarkShift;  // block marks of one bin (8)
+    __shared__ uint32_t bmark[kBinMarks];
     constexpr int kWaves = kResolveThreads / 64;
     constexpr int kWordsPerWave = kBinVerts / 64 / kWaves;  // 32: word wid + kWaves * k of the bin
     constexpr int kPairUnroll = 8;
@@ -892,6 +894,7 @@ __global__ __launch_bounds__(kResolveThreads) void bin_resolve_kernel(ResolveArg
         const uint64_t visv = mine ? a.pi[myw] : ~0ull;
         const uint64_t nv = mine ? a.N[myw] : 0ull;
         for (int i = tid; i < kBinVerts; i += kResolveThreads) best[i] = -1;
+        if (tid < kBinMarks) bmark[tid] = 0;
         __syncthreads();
         const uint64_t *pb = a.bpairs + b * kBinGrid * a.cseg;
         for (int32_t i0 = 0; i0 < total; i0 += kPairUnroll * kResolveThreads) {
@@ -937,11 +940,13 @@ __global__ __launch_bounds__(kResolveThreads) void bin_resolve_kernel(ResolveArg
                 const uint64_t bits = __ballot(open && m >= 0) | old;
                 if (lane == 0 && bits != old) {
                     a.N[gw] = bits;
-                    a.marks_next.mark_word(gw);
+                    bmark[wl >> kMarkShift] = 1u;
                 }
             }
         }
-        __syncthreads();  // best, spre and wtot are used again
+        __syncthreads();  // best, spre, wtot and bmark are used again
+        // the bin's block marks, one store each (no read: a set mark stays set)
+        if (tid < kBinMarks && bmark[tid]) a.marks_next.m[(w0 >> kMarkShift) + tid] = 1u;
     }
 }
 
@@ -1410,9 +1415,11 @@ int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *
     }
     y.flags = c.flags;
     // Beamer's parameters of the per-level direction choice, measured best
-    // on R-MAT graphs of scale 22 (4 x 4) and 26 (8 x 8)
+    // on R-MAT graphs of scale 22 (4 x 4) and 26 (8 x 8): beta 48 keeps a
+    // shrinking frontier of a few million low-degree vertices bottom-up,
+    // where the pull finds the few remaining vertices cheaply
     y.alpha = c.alpha == 0.f && c.beta == 0.f ? 16.0f : c.alpha;
-    y.beta = c.beta == 0.f ? 24.0f : c.beta;
+    y.beta = c.beta == 0.f ? 48.0f : c.beta;
     int64_t o = 0;
     auto take = [&o](int64_t bytes) {
         const int64_t at = o;
