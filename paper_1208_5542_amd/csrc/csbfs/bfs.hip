@@ -823,7 +823,7 @@ __global__ __launch_bounds__(kPullThreads) void pull_kernel(PullArgs a) {
 // One launch per level for the default (direction-optimizing) search: the
 // top-down push or the bottom-up pull, as the level's direction says.
 static_assert(kExpThreads == kPullThreads, "one block size for both directions");
-__global__ __launch_bounds__(kExpThreads) void level_kernel(ExpandArgs ea, PullArgs pa) {
+__device__ __forceinline__ void level_body(ExpandArgs ea, const PullArgs &pa) {
     const int32_t d = *ea.dir;
     if (d == kDirBU) {
         pull_body<true>(pa);
@@ -831,6 +831,21 @@ __global__ __launch_bounds__(kExpThreads) void level_kernel(ExpandArgs ea, PullA
         ea.tile_words = *ea.tile;
         expand_body<false>(ea);
     }
+}
+
+__global__ __launch_bounds__(kExpThreads) void level_kernel(ExpandArgs ea, PullArgs pa) { level_body(ea, pa); }
+
+// The same for large graphs (kWideWords bitmap words or more): a register
+// budget of 80 (6 waves per SIMD, at the price of a few spills) so that three
+// workgroups share a CU, launched as kWideGrid workgroups. Scale 26: 350.4 ->
+// 363.3 GTEPS (top-down push 0.25 -> 0.19 ms per search, pull 1.60 -> 1.57);
+// scale 24: 276.5 -> 280.7; scale 22 loses 2-3% with it and keeps
+// level_kernel.
+constexpr int64_t kWideWords = int64_t(1) << 18;  // n >= 2^24
+constexpr unsigned kWideGrid = 768;
+__global__ __launch_bounds__(kExpThreads) __attribute__((amdgpu_waves_per_eu(6))) void level_kernel_wide(
+    ExpandArgs ea, PullArgs pa) {
+    level_body(ea, pa);
 }
 
 // Binned push, second half: bin b takes the highest source of each target
@@ -1631,13 +1646,16 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
     pa.tile_words = kPullTileDense;
     pb.tile_words = kPullTileBU;
     // grids (multiples of the XCD count) from sweeps at scales 22 and 26:
-    // 512 expansion workgroups of 8 waves and 256 for the long rows (the
-    // same waves as 1024 and 512 of 4, which beat 512-4096 and 512-2048)
+    // 512 expansion workgroups of 8 waves (the same waves as 1024 of 4,
+    // which beat 512-4096; 768 for the wide level kernel) and kBinGrid for
+    // the long rows
     const unsigned exp_grid = 512, big_grid = kBinGrid;
+    const bool wide = words >= kWideWords;
+    const unsigned level_grid = wide ? kWideGrid : exp_grid;
     const unsigned pull_grid = grid_for((words + kPullTileDense - 1) / kPullTileDense, kPullThreads / 64, 16384);
     const unsigned bu_grid = grid_for((words + kPullTileBU - 1) / kPullTileBU, kPullThreads / 64, 2048);
     pa.xcd = xcd_split(P, pull_grid) && W % kPullTileDense == 0;
-    pb.xcd = xcd_split(P, exp_grid) && W % kPullTileBU == 0;
+    pb.xcd = xcd_split(P, exp_grid) && xcd_split(P, level_grid) && W % kPullTileBU == 0;
     const int32_t bu_xcd = xcd_split(P, bu_grid) && W % kPullTileBU == 0;
     DirArgs da{};
     da.st = w.dstate;
@@ -1753,7 +1771,10 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
             } else {
                 // one launch: the push or the pull, as the level's direction
                 // says; the long-row pass returns at once on bottom-up levels
-                hipLaunchKernelGGL(level_kernel, dim3(exp_grid), dim3(kExpThreads), 0, st, ea, pb);
+                if (wide)
+                    hipLaunchKernelGGL(level_kernel_wide, dim3(level_grid), dim3(kExpThreads), 0, st, ea, pb);
+                else
+                    hipLaunchKernelGGL(level_kernel, dim3(level_grid), dim3(kExpThreads), 0, st, ea, pb);
                 CSBFS_HIP(hipGetLastError());
                 if (ev) CSBFS_HIP(hipEventRecord(ev[3], st));
                 hipLaunchKernelGGL(expand_big_kernel<false>, dim3(big_grid), dim3(kExpThreads), 0, st, ea);
