@@ -1021,7 +1021,11 @@ __device__ void choose_direction(const DirArgs &a, unsigned long long nf, unsign
     *a.rec = next | (s.bin << 8);  // direction, and the binned push in bit 8
 }
 
-constexpr int64_t kDecGridChunks = 8;  // decode workgroups per stream, each looping over chunks (8 beat 16, 32, 64)
+// decode workgroups per stream, each looping over chunks: 12, with a register
+// budget of 80 (three workgroups per CU; 97 registers gave two): scale 26
+// 362.0 -> 368.3 GTEPS (decode 0.272 -> 0.233 ms per search), scale 22
+// 158.5 -> 160.2; at two per CU 8 had beaten 16, 32 and 64
+constexpr int64_t kDecGridChunks = 12;
 constexpr int kUpdWords = 8;  // bitmap words per wavefront step of the update (8 beat 4, 16, 32)
 // Groups per encoder thread of a search: 2 (segments of 1024 groups) when
 // segments of 2048 would leave fewer than two workgroups per CU, else 4.
@@ -1211,7 +1215,7 @@ struct ReduceArgs {
 // chooses the direction of the expansion of f^k. A workgroup that starts
 // after that choice and finds the idle direction has an empty frontier's
 // streams to decode, which set no bit: returning is the same.
-__global__ __launch_bounds__(kDecThreads) void search_decode_kernel(WahBatch b, ReduceArgs r) {
+__global__ __launch_bounds__(kDecThreads) __attribute__((amdgpu_waves_per_eu(6))) void search_decode_kernel(WahBatch b, ReduceArgs r) {
     if (r.dir.st->cur == kDirIdle) return;
     if (blockIdx.x == 0 && blockIdx.y == 0) {
         unsigned long long nf = 0, mf = 0;
