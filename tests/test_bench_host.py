@@ -42,5 +42,7 @@ def test_committed_counters_are_consistent():
         assert os.path.exists(os.path.join(bench.REPO, ent["summary"])), name
         parts = ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"]
         assert abs(ent["bytes_per_launch"] - parts) <= 1, name
-        # the kernels of one expansion step (the resolve of the binned push too)
-        assert ent["kernels"] == ["level_kernel", "expand_big_kernel", "bin_resolve_kernel"], name
+        # the kernels of one expansion step (the level kernel under its name for
+        # large graphs, and the resolve of the binned push)
+        assert ent["kernels"][0] in ("level_kernel", "level_kernel_wide"), name
+        assert ent["kernels"][1:] == ["expand_big_kernel", "bin_resolve_kernel"], name
