@@ -631,7 +631,8 @@ def main():
                                  "receives over one whole search"},
         "roofline": {"bound": "hbm",
                      "kernel": "expansion step of one level: level_kernel (top-down push or bottom-up pull, "
-                               "chosen per level) + expand_big_kernel (top-down long rows; on binned levels "
+                               "chosen per level; level_kernel_wide on graphs of 2^24 vertices or more) + "
+                               "expand_big_kernel (top-down long rows; on binned levels "
                                "their pairs go into bins) + bin_resolve_kernel (binned levels); time = the "
                                "kernels' own HIP-event intervals on the library's stream",
                      "achieved": exp["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": exp["frac"],
