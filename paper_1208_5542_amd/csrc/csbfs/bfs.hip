@@ -1184,8 +1184,8 @@ struct FrontierHook {
 // Update + sieve + compress of level k (k >= 1): one workgroup per (stream,
 // segment). Returns at once once the search has ended.
 template <int kGpt>
-__global__ __launch_bounds__(kEncThreads) void frontier_encode_kernel(WahBatch b, FrontierHook h,
-                                                                      const DirState *st, int32_t split) {
+__device__ __forceinline__ void frontier_encode_body(const WahBatch &b, FrontierHook &h, const DirState *st,
+                                                     int32_t split) {
     const int32_t d = st->cur;  // the direction f^(k-1) was expanded in
     if (d == kDirIdle) return;
     h.clear_views = d != kDirTD;  // the sparse push zeroes the view words it reads
@@ -1194,6 +1194,23 @@ __global__ __launch_bounds__(kEncThreads) void frontier_encode_kernel(WahBatch b
     bool first;
     enc_stream_of(blockIdx.x, b.P, b.nseg, split != 0, s, first);
     encode_segment<kGpt>(b, h, s, first);
+}
+
+// Segments of 1024 groups: the grids of smaller graphs (fewer workgroups than
+// the GPU holds), where the register budget below only costs spills.
+__global__ __launch_bounds__(kEncThreads) void frontier_encode_kernel_g2(WahBatch b, FrontierHook h,
+                                                                      const DirState *st, int32_t split) {
+    frontier_encode_body<2>(b, h, st, split);
+}
+
+// Segments of 2048 groups, for large graphs: 8 waves per SIMD (the 106
+// scalar registers it would take allow 7; the spilled ones go to vector
+// lanes) so that four workgroups share a CU, their 37 KiB of LDS each
+// fitting. Scale 26, 16 roots: encoder 0.532 -> 0.497 ms per search, 367.6
+// -> 373.1 GTEPS.
+__global__ __launch_bounds__(kEncThreads) __attribute__((amdgpu_waves_per_eu(8))) void frontier_encode_kernel_g4(
+    WahBatch b, FrontierHook h, const DirState *st, int32_t split) {
+    frontier_encode_body<4>(b, h, st, split);
 }
 
 struct ReduceArgs {
@@ -1714,10 +1731,10 @@ int run_search(const csbfs_graph *g, const SearchLayout &y, const SearchState &w
             FrontierHook fh{w.nb[j & 1], w.nb[(j + 1) & 1], w.pi, w.view, level, g->deg, w.part,
                             marks_of(j), marks_of(j + 1), W, y.seg_words, (int32_t)P, (int32_t)j, 1, 1};
             if (y.enc_gpt == 2)
-                hipLaunchKernelGGL(frontier_encode_kernel<2>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
+                hipLaunchKernelGGL(frontier_encode_kernel_g2, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
                                    (const DirState *)w.dstate, enc_split);
             else
-                hipLaunchKernelGGL(frontier_encode_kernel<4>, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
+                hipLaunchKernelGGL(frontier_encode_kernel_g4, enc_grid, dim3(kEncThreads), 0, st, wb, fh,
                                    (const DirState *)w.dstate, enc_split);
             CSBFS_HIP(hipGetLastError());
             if (ev) CSBFS_HIP(hipEventRecord(ev[1], st));

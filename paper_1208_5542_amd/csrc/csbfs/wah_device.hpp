@@ -337,7 +337,10 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
     constexpr int kLds = enc_lds_words(kSeg);
     __shared__ uint64_t sw[kLds];
     __shared__ uint64_t su[kLds];
-    __shared__ int starts[kSeg];
+    // groups that start a word, relative to the segment's first group (16
+    // bits, so that four workgroups of the encoder fit a CU's LDS)
+    static_assert(kSeg <= 65536, "16-bit group offsets");
+    __shared__ uint16_t starts[kSeg];
     __shared__ int sh_last_cls;
     __shared__ uint64_t sh_prefix;
     __shared__ uint32_t sh_ticket;
@@ -406,7 +409,7 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
             sh_clean_words = nflag;
             if (nflag) {
                 sh_last_cls = cls[0];
-                starts[0] = (int)xa;
+                starts[0] = (uint16_t)(xa - g.x0);
             }
         }
         __syncthreads();
@@ -417,7 +420,7 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
         for (int k = 0; k < kGpt; ++k) {
             if (cls[k] < 0) continue;
             if (pos == seg_words - 1) sh_last_cls = cls[k];
-            starts[pos++] = (int)(xa + k);
+            starts[pos++] = (uint16_t)(xa + k - g.x0);
         }
         __syncthreads();
     }
@@ -427,7 +430,7 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
     // it publishes its (empty) aggregate and needs no prefix
     const bool quiet = clean && seg_words == 0 && !g.last && seg > 0;
     if (threadIdx.x < 64) {
-        const uint64_t mine = lb_value(seg_words, seg_words ? starts[seg_words - 1] : 0, sh_last_cls);
+        const uint64_t mine = lb_value(seg_words, seg_words ? g.x0 + starts[seg_words - 1] : 0, sh_last_cls);
         if (quiet) {
             if (threadIdx.x == 0) {
                 __hip_atomic_store(&look[seg], mine | kLbAgg | ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -467,7 +470,7 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
         if (cls[k] == 2) {
             out[offset + pos] = __builtin_bitreverse64(val[k]) >> 1;  // bit (62 - t) = group bit t
         } else if (pos + 1 < seg_words || g.last) {
-            const int64_t end = pos + 1 < seg_words ? starts[pos + 1] : g.G;
+            const int64_t end = pos + 1 < seg_words ? g.x0 + starts[pos + 1] : g.G;
             out[offset + pos] = kFillFlag | (cls[k] == 1 ? kFillBit : 0) | (uint64_t)(end - gx);
         }
         ++pos;
@@ -478,7 +481,7 @@ __device__ __forceinline__ void encode_segment(const WahBatch &b, Hook &hook, in
         const int prev_cls = (int)((pre >> (2 * kLbBits)) & 3);
         if (fits && offset >= 1 && (pre & kLbHasLast) && prev_cls != 2 && (seg_words > 0 || g.last)) {
             const int64_t begin = (int64_t)((pre >> kLbBits) & kLbField);
-            const int64_t end = seg_words > 0 ? starts[0] : g.G;
+            const int64_t end = seg_words > 0 ? g.x0 + starts[0] : g.G;
             out[offset - 1] = kFillFlag | (prev_cls == 1 ? kFillBit : 0) | (uint64_t)(end - begin);
             if (cstart && (offset - 1) % kDecChunk == 0) cstart[(offset - 1) / kDecChunk] = begin;
         }
