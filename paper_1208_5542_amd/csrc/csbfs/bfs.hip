@@ -1441,6 +1441,10 @@ int search_layout(int64_t n, int32_t p, int64_t nnz, const csbfs_search_config *
     if (y.nbins) {
         y.bin_cap = cap0;
         y.cseg = ((y.bin_cap + y.nbins * kBinGrid - 1) / (y.nbins * kBinGrid) + 7) / 8 * 8;
+        // a workgroup counts its pairs per bin in 16 bits, saturating at
+        // 65535: segments stay below that, so every pair counted past a
+        // segment's end goes to the atomic push
+        y.cseg = std::min<int64_t>(y.cseg, 65528);
         y.bin_min = forced ? 0ull : kBinMinEdges;
         y.bin_deg = forced ? 0ull : kBinMinDegree;
         y.bin_limit = (unsigned long long)(forced ? y.bin_cap : y.bin_cap / 2);

@@ -168,6 +168,11 @@ def test_layout_query_is_host_only_and_exact_in_its_inputs():
     big = csbfs.layout_query(1 << 22, 1 << 26, 4, csbfs.search_config(flags=binned, push_bin_pairs=1 << 24))
     assert atomic["workspace_bytes"] < small["workspace_bytes"] < big["workspace_bytes"]
     assert big["workspace_bytes"] - small["workspace_bytes"] >= 8 * ((1 << 24) - (1 << 20))
+    # segments stay below the workgroups' 16-bit pair counts: a huge capacity
+    # on a one-bin graph gives 512 segments of at most 65528 pairs
+    huge = csbfs.layout_query(1 << 12, 100, 4, csbfs.search_config(flags=binned, push_bin_pairs=(1 << 31) - 1))
+    none = csbfs.layout_query(1 << 12, 100, 4, csbfs.search_config(flags=csbfs.FLAG_ATOMIC_PUSH))
+    assert 0 < huge["workspace_bytes"] - none["workspace_bytes"] <= 8 * 512 * 65528 + 4 * 512 + 2 * 256
     # a graph with 2^31 entries gets bins by default
     large = csbfs.layout_query(1 << 26, 1 << 30, 8)
     large_atomic = csbfs.layout_query(1 << 26, 1 << 30, 8, csbfs.search_config(flags=csbfs.FLAG_ATOMIC_PUSH))
