@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 
 def _ensure_built():
-    """Build what is missing (and only that); the driver builds everything."""
+    """Build what is missing (and only that); __graft_entry__.build() compiles everything."""
     if not os.path.exists(os.path.join(REPO, "oracle", "liboracle.so")):
         from oracle import build as ob
         ob.build()
