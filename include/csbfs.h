@@ -278,10 +278,10 @@ int csbfs_layout_query(int64_t n, int64_t n_tuples, int32_t p, const csbfs_searc
  * non-zero, the p frontier views (p * n bits), the WAH stream arena (p * p
  * streams of floor((n/p)/63) + 1 words, times max_levels with
  * CSBFS_FLAG_KEEP_STREAMS), the expansion work queue, the binned push's
- * bins (none with CSBFS_FLAG_ATOMIC_PUSH) and the per-level
- * counters for up to max_levels levels (1 <= max_levels <= 65536); plus a
- * pinned two-word mailbox and, with CSBFS_FLAG_TIMING, five events per
- * level. The graph must outlive the engine. The encoder's segment size is
+ * bins (only where a level can be binned, see CSBFS_FLAG_BINNED_PUSH) and
+ * the per-level counters for up to max_levels levels (1 <= max_levels <=
+ * 65536); plus a pinned two-word mailbox and, with CSBFS_FLAG_TIMING, five
+ * events per level. The graph must outlive the engine. The encoder's segment size is
  * chosen from n/p and p. Errors: EINVAL, EHIP.
  */
 int csbfs_engine_create(const csbfs_graph *g, int32_t max_levels, uint32_t flags,
